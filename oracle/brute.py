@@ -1,0 +1,70 @@
+"""Brute-force subsequence DTW by enumerating every warping path.
+
+TEST INFRASTRUCTURE ONLY (tiny inputs).  Independent of the recurrence in
+dtw_oracle.c: instead of a table it walks every path explicitly.
+
+A path (RawAlign Sec. 2.2: each step comes from the north, north-west or west
+neighbour) is a sequence of cells that starts in row 0 at any column, moves by
+(1,0), (0,1) or (1,1), and stops at any cell of row n-1.  Its cost is the sum
+of |q_i - r_j| over its cells, accumulated in path order in double precision.
+The subsequence DTW cost is the smallest path cost; the end is the smallest
+final column among the cheapest paths.
+
+Because a rounded addition is monotone, the table recurrence returns exactly
+the smallest rounded path sum, so this enumeration matches it bit for bit on
+any input, not only on exactly representable ones.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+
+def enumerate_paths(n: int, m: int):
+    """Yield every path as a list of (i, j) cells (small n, m only)."""
+    path = []
+
+    def walk(i, j):
+        path.append((i, j))
+        if i == n - 1:
+            yield list(path)
+        if i + 1 < n:
+            yield from walk(i + 1, j)
+        if j + 1 < m:
+            yield from walk(i, j + 1)
+        if i + 1 < n and j + 1 < m:
+            yield from walk(i + 1, j + 1)
+        path.pop()
+
+    for j0 in range(m):
+        yield from walk(0, j0)
+
+
+def brute_dtw(q, r):
+    """(cost, end, number of paths) by explicit path enumeration."""
+    q = [float(x) for x in q]
+    r = [float(x) for x in r]
+    n, m = len(q), len(r)
+    if n == 0:
+        return 0.0, -1, 0
+    if m == 0:
+        return math.inf, -1, 0
+    sys.setrecursionlimit(max(1000, 4 * (n + m) + 100))
+    best = math.inf
+    best_end = -1
+    count = 0
+    # Depth-first walk with the running sum, so paths are not materialised.
+    stack = [(0, j0, abs(q[0] - r[j0])) for j0 in reversed(range(m))]
+    while stack:
+        i, j, acc = stack.pop()
+        if i == n - 1:
+            count += 1
+            if acc < best or (acc == best and j < best_end):
+                best, best_end = acc, j
+        if i + 1 < n:
+            stack.append((i + 1, j, acc + abs(q[i + 1] - r[j])))
+        if j + 1 < m:
+            stack.append((i, j + 1, acc + abs(q[i] - r[j + 1])))
+        if i + 1 < n and j + 1 < m:
+            stack.append((i + 1, j + 1, acc + abs(q[i + 1] - r[j + 1])))
+    return best, best_end, count

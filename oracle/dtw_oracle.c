@@ -1,0 +1,279 @@
+/*
+ * dtw_oracle.c -- CPU oracle for subsequence dynamic time warping (DTW).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path
+ * (the HIP library) shares no code, header, table or helper with it.
+ *
+ * What it computes (RawAlign, arXiv 2310.05037, Sec. 2.2 "Alignment via
+ * Dynamic Time Warping"): a two-dimensional dynamic-programming table in
+ * which every entry adds the numerical difference of the two signal values
+ * (no fixed indel penalty) to the smallest of its north, north-west and west
+ * neighbours.  The paper aligns a read's events against a candidate region
+ * that is longer than the read, so the query must be aligned whole while the
+ * alignment may start and end anywhere in the region (subsequence DTW, the
+ * textbook form in Mueller, "Fundamentals of Music Processing", 2015, Ch. 7):
+ *
+ *   c(i,j)  = |q_i - r_j|                 (float inputs widened exactly)
+ *   D(-1,j) = 0          for j = -1..m-1  (free start anywhere in the region)
+ *   D(i,-1) = +inf       for i >= 0
+ *   D(i,j)  = c(i,j) + min{ D(i-1,j-1), D(i-1,j), D(i,j-1) }
+ *   C_DTW   = min_j D(n-1,j),   end = smallest j attaining it.
+ *
+ * Degenerate inputs: n == 0 gives cost 0 and end -1; m == 0 (with n > 0)
+ * gives cost +inf and end -1.
+ *
+ * Streaming (Read Until chunks, Sec. 1 and Sec. 3.1.2): when a previous
+ * chunk's last row is supplied as row -1, D(-1,j) = row[j] for j >= 0 and the
+ * corner D(-1,-1) is +inf, because column -1 is +inf for every real row.
+ * The result then equals the definition applied to the concatenated prefix.
+ *
+ * Precision: the reference is double precision.  A float instantiation of
+ * the same recurrence is provided as well: every cell is one rounded
+ * subtraction, an exact absolute value, an exact minimum and one rounded
+ * addition, so any evaluation order of the table gives bit-identical float
+ * results, which makes the float version a bitwise check for GPU code.
+ * Build without -ffast-math and without floating-point contraction.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static double min3_d(double a, double b, double c)
+{
+    double x = a < b ? a : b;
+    return x < c ? x : c;
+}
+
+static float min3_f(float a, float b, float c)
+{
+    float x = a < b ? a : b;
+    return x < c ? x : c;
+}
+
+/*
+ * One pair in double precision.
+ *   q[0..n), r[0..m): inputs (float, widened to double).
+ *   init_row: NULL for a fresh alignment (row -1 all zero), else the m
+ *             values of the previous chunk's last row (corner +inf).
+ *   last_row: optional output, the m values of row n-1 (or of row -1 when
+ *             n == 0).
+ *   end:      output, smallest j of the minimum in row n-1 (-1 if none).
+ * Returns C_DTW.  Returns NaN and end = -2 if memory runs out.
+ */
+double oracle_dtw_f64(const float *q, int64_t n, const float *r, int64_t m,
+                      const double *init_row, double *last_row, int32_t *end)
+{
+    if (m == 0) {
+        *end = -1;
+        return n == 0 ? 0.0 : INFINITY;
+    }
+    /* prev[j+1] holds D(i-1, j); prev[0] holds D(i-1, -1). */
+    double *prev = malloc((size_t)(m + 1) * sizeof(double));
+    double *cur = malloc((size_t)(m + 1) * sizeof(double));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        *end = -2;
+        return NAN;
+    }
+    if (init_row) {
+        prev[0] = INFINITY;
+        for (int64_t j = 0; j < m; ++j)
+            prev[j + 1] = init_row[j];
+    } else {
+        for (int64_t j = 0; j <= m; ++j)
+            prev[j] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY; /* D(i, -1) */
+        double qi = (double)q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            double c = fabs(qi - (double)r[j]);
+            cur[j + 1] = c + min3_d(prev[j], prev[j + 1], cur[j]);
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    double best;
+    int32_t arg;
+    if (n == 0 && !init_row) {
+        best = 0.0;
+        arg = -1;
+    } else {
+        best = prev[1];
+        arg = 0;
+        for (int64_t j = 1; j < m; ++j) {
+            if (prev[j + 1] < best) {
+                best = prev[j + 1];
+                arg = (int32_t)j;
+            }
+        }
+    }
+    if (last_row)
+        for (int64_t j = 0; j < m; ++j)
+            last_row[j] = prev[j + 1];
+    free(prev);
+    free(cur);
+    *end = arg;
+    return best;
+}
+
+/* The same recurrence with every value held in float. */
+float oracle_dtw_f32(const float *q, int64_t n, const float *r, int64_t m,
+                     const float *init_row, float *last_row, int32_t *end)
+{
+    if (m == 0) {
+        *end = -1;
+        return n == 0 ? 0.0f : INFINITY;
+    }
+    float *prev = malloc((size_t)(m + 1) * sizeof(float));
+    float *cur = malloc((size_t)(m + 1) * sizeof(float));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        *end = -2;
+        return NAN;
+    }
+    if (init_row) {
+        prev[0] = INFINITY;
+        for (int64_t j = 0; j < m; ++j)
+            prev[j + 1] = init_row[j];
+    } else {
+        for (int64_t j = 0; j <= m; ++j)
+            prev[j] = 0.0f;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        float qi = q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            float d = qi - r[j];
+            float c = fabsf(d);
+            cur[j + 1] = c + min3_f(prev[j], prev[j + 1], cur[j]);
+        }
+        float *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    float best;
+    int32_t arg;
+    if (n == 0 && !init_row) {
+        best = 0.0f;
+        arg = -1;
+    } else {
+        best = prev[1];
+        arg = 0;
+        for (int64_t j = 1; j < m; ++j) {
+            if (prev[j + 1] < best) {
+                best = prev[j + 1];
+                arg = (int32_t)j;
+            }
+        }
+    }
+    if (last_row)
+        for (int64_t j = 0; j < m; ++j)
+            last_row[j] = prev[j + 1];
+    free(prev);
+    free(cur);
+    *end = arg;
+    return best;
+}
+
+/*
+ * Full table D(i,j), row-major n x m, double precision, fresh alignment.
+ * For small inputs in tests of the table's own invariants.
+ */
+void oracle_dtw_matrix_f64(const float *q, int64_t n, const float *r, int64_t m,
+                           double *D)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            double diag = (i == 0) ? 0.0 : (j == 0 ? INFINITY : D[(i - 1) * m + j - 1]);
+            double up = (i == 0) ? 0.0 : D[(i - 1) * m + j];
+            double left = (j == 0) ? INFINITY : D[i * m + j - 1];
+            double c = fabs((double)q[i] - (double)r[j]);
+            D[i * m + j] = c + min3_d(diag, up, left);
+        }
+    }
+}
+
+/* ---- batches: pairs are independent, threads take pairs from a counter ---- */
+
+struct batch_job {
+    const float *q;
+    const int64_t *q_off;
+    const int32_t *q_len;
+    const float *r;
+    const int64_t *r_off;
+    const int32_t *r_len;
+    int64_t n_pairs;
+    double *out64;
+    float *out32;
+    int32_t *out_end;
+    int64_t next;
+};
+
+static void *batch_worker(void *arg)
+{
+    struct batch_job *job = arg;
+    for (;;) {
+        int64_t p = __atomic_fetch_add(&job->next, 1, __ATOMIC_RELAXED);
+        if (p >= job->n_pairs)
+            break;
+        const float *qp = job->q + job->q_off[p];
+        const float *rp = job->r + job->r_off[p];
+        if (job->out64)
+            job->out64[p] = oracle_dtw_f64(qp, job->q_len[p], rp, job->r_len[p],
+                                           NULL, NULL, &job->out_end[p]);
+        else
+            job->out32[p] = oracle_dtw_f32(qp, job->q_len[p], rp, job->r_len[p],
+                                           NULL, NULL, &job->out_end[p]);
+    }
+    return NULL;
+}
+
+static int run_batch(struct batch_job *job, int n_threads)
+{
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > 256)
+        n_threads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 1; t < n_threads; ++t) {
+        if (pthread_create(&th[started], NULL, batch_worker, job) != 0)
+            break;
+        ++started;
+    }
+    batch_worker(job);
+    for (int t = 0; t < started; ++t)
+        pthread_join(th[t], NULL);
+    return started + 1; /* threads that actually worked */
+}
+
+/*
+ * Pair p aligns q[q_off[p] .. +q_len[p]) against r[r_off[p] .. +r_len[p]).
+ * Returns the number of threads used.
+ */
+int oracle_dtw_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_len,
+                         const float *r, const int64_t *r_off, const int32_t *r_len,
+                         int64_t n_pairs, double *out_score, int32_t *out_end,
+                         int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            out_score, NULL, out_end, 0};
+    return run_batch(&job, n_threads);
+}
+
+int oracle_dtw_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_len,
+                         const float *r, const int64_t *r_off, const int32_t *r_len,
+                         int64_t n_pairs, float *out_score, int32_t *out_end,
+                         int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            NULL, out_score, out_end, 0};
+    return run_batch(&job, n_threads);
+}

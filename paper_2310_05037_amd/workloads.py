@@ -1,0 +1,309 @@
+"""Seeded synthetic workloads shaped like RawAlign's alignment inputs.
+
+This module only draws random numbers and packs arrays; it holds none of the
+alignment arithmetic, so the CPU oracle and the GPU path can both be fed from
+it.  The paper maps R9.4 nanopore reads (Tab. 1) that are not available here;
+these generators stand in for them with the same structure:
+
+* a reference of random bases turned into expected event levels by a pore
+  model that maps each 6-mer to one level (Supp. A.1.1); the model here is
+  4,096 levels drawn from N(0, 1);
+* a read is a window of the reference whose k-mers are emitted as events:
+  each k-mer is skipped with probability 0.05, otherwise it dwells for a
+  Geometric(0.3) number of events, each event being the level plus N(0, 0.1)
+  noise (Supp. A.2 segmentation averages samples into such events);
+* a read is aligned against candidate regions (Sec. 2.1.3); one region per
+  read contains the read's source window, the others are uniform decoys.
+
+Every configuration uses numpy's PCG64 with seed 2310050370 + its index.
+Regions are (offset, length) slices of the one reference level array; the
+candidates of a read share the read's query slice.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 2310050370
+K = 6
+N_KMERS = 4 ** K
+SKIP_P = 0.05
+DWELL_P = 0.3
+NOISE_SD = 0.1
+
+
+@dataclass
+class Batch:
+    """Packed (read, candidate) pairs.  Pair p aligns
+    q[q_off[p] : q_off[p]+q_len[p]] against r[r_off[p] : r_off[p]+r_len[p]]."""
+    name: str
+    q: np.ndarray        # float32 read events, reads concatenated
+    r: np.ndarray        # float32 reference levels
+    q_off: np.ndarray    # int64 per pair
+    q_len: np.ndarray    # int32 per pair
+    r_off: np.ndarray    # int64 per pair
+    r_len: np.ndarray    # int32 per pair
+    cand_off: np.ndarray  # int64 per read: first pair of the read
+    cand_cnt: np.ndarray  # int32 per read: candidates of the read
+    n_events: np.ndarray  # int32 per read
+    true_pair: np.ndarray  # int64 per read: the pair holding the source window
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_pairs(self) -> int:
+        return int(len(self.q_off))
+
+    @property
+    def cells(self) -> int:
+        return int(np.dot(self.q_len.astype(np.int64), self.r_len.astype(np.int64)))
+
+    def subset(self, pairs) -> "Batch":
+        """Pairs `pairs` as single-candidate reads over the same q and r arrays."""
+        pairs = np.asarray(pairs, dtype=np.int64)
+        k = len(pairs)
+        return Batch(self.name + "[subset]", self.q, self.r, self.q_off[pairs].copy(),
+                     self.q_len[pairs].copy(), self.r_off[pairs].copy(), self.r_len[pairs].copy(),
+                     np.arange(k, dtype=np.int64), np.ones(k, dtype=np.int32),
+                     self.q_len[pairs].copy(), np.arange(k, dtype=np.int64), dict(self.meta))
+
+    def manifest(self) -> dict:
+        h = hashlib.sha256()
+        for a in (self.q, self.r, self.q_off, self.q_len, self.r_off, self.r_len):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return {"name": self.name, "pairs": self.n_pairs, "reads": int(len(self.cand_off)),
+                "cells": self.cells, "sha256": h.hexdigest(), **self.meta}
+
+
+def rng_for(config_index: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + config_index))
+
+
+def pore_model(rng) -> np.ndarray:
+    return rng.standard_normal(N_KMERS).astype(np.float32)
+
+
+def random_bases(rng, length: int) -> np.ndarray:
+    return rng.integers(0, 4, size=length, dtype=np.uint8)
+
+
+def expected_levels(bases: np.ndarray, model: np.ndarray) -> np.ndarray:
+    """Level of every 6-mer of `bases` (length len(bases) - 5), float32."""
+    L = len(bases) - K + 1
+    idx = np.zeros(max(L, 0), dtype=np.int64)
+    for t in range(K):
+        idx = idx * 4 + bases[t:t + L].astype(np.int64)
+    return model[idx]
+
+
+def read_events(rng, levels: np.ndarray, start: int, n_events: int | None = None,
+                n_kmers: int | None = None) -> tuple[np.ndarray, int]:
+    """Events of a read whose first k-mer is levels[start].
+
+    Either emit exactly `n_events` events (the read is cut there) or walk
+    `n_kmers` k-mers.  Returns (events float32, number of k-mers covered)."""
+    if n_kmers is None:
+        guess = int(n_events / ((1 - SKIP_P) / DWELL_P)) + 64
+        while True:
+            kk = min(guess, len(levels) - start)
+            dwell = rng.geometric(DWELL_P, size=kk)
+            dwell[rng.random(kk) < SKIP_P] = 0
+            cs = np.cumsum(dwell)
+            if cs[-1] >= n_events or kk == len(levels) - start:
+                break
+            guess *= 2
+        used = int(np.searchsorted(cs, n_events)) + 1 if cs[-1] >= n_events else kk
+        dwell = dwell[:used]
+        lv = np.repeat(levels[start:start + used], dwell)[:n_events]
+    else:
+        used = n_kmers
+        dwell = rng.geometric(DWELL_P, size=used)
+        dwell[rng.random(used) < SKIP_P] = 0
+        lv = np.repeat(levels[start:start + used], dwell)
+    ev = lv.astype(np.float64) + rng.normal(0.0, NOISE_SD, size=len(lv))
+    return ev.astype(np.float32), used
+
+
+def _pack(name, reads, pairs, r, meta) -> Batch:
+    """reads: list of event arrays; pairs: list of (read index, r_off, r_len, is_true)."""
+    q_lens = np.array([len(x) for x in reads], dtype=np.int64)
+    q_starts = np.concatenate([[0], np.cumsum(q_lens)[:-1]]).astype(np.int64)
+    q = np.concatenate(reads).astype(np.float32) if reads else np.zeros(0, np.float32)
+    pr = np.array([p[0] for p in pairs], dtype=np.int64)
+    q_off = q_starts[pr]
+    q_len = q_lens[pr].astype(np.int32)
+    r_off = np.array([p[1] for p in pairs], dtype=np.int64)
+    r_len = np.array([p[2] for p in pairs], dtype=np.int32)
+    n_reads = len(reads)
+    cand_cnt = np.bincount(pr, minlength=n_reads).astype(np.int32)
+    cand_off = np.concatenate([[0], np.cumsum(cand_cnt)[:-1]]).astype(np.int64)
+    true_pair = np.full(n_reads, -1, dtype=np.int64)
+    for k, p in enumerate(pairs):
+        if p[3]:
+            true_pair[p[0]] = k
+    return Batch(name, q, r, q_off, q_len, r_off, r_len, cand_off, cand_cnt,
+                 q_lens.astype(np.int32), true_pair, meta)
+
+
+def _true_region(rng, span_start, span_len, m, L):
+    """Region of m levels containing [span_start, span_start+span_len) when possible."""
+    slack = max(m - span_len, 0)
+    off = span_start - int(rng.integers(0, slack + 1))
+    return int(min(max(off, 0), max(L - m, 0)))
+
+
+def config0(seed_index: int = 0) -> Batch:
+    """Plain single read: 10 kb reference, one read from a random 500-base
+    window, 10 candidate regions of 900 bases (1 true, 9 random)."""
+    rng = rng_for(seed_index)
+    model = pore_model(rng)
+    bases = random_bases(rng, 10_000)
+    r = expected_levels(bases, model)
+    L = len(r)
+    win = 500
+    w0 = int(rng.integers(0, len(bases) - win + 1))
+    ev, _ = read_events(rng, r, w0, n_kmers=win - K + 1)
+    m = 900 - K + 1
+    true_off = w0 - int(rng.integers(0, 400 + 1))
+    true_off = min(max(true_off, 0), L - m)
+    pairs = [(0, true_off, m, True)]
+    for _ in range(9):
+        pairs.append((0, int(rng.integers(0, L - m + 1)), m, False))
+    return _pack("config0_single_read", [ev], pairs, r,
+                 {"config": 0, "window_start": w0, "reference_bases": len(bases)})
+
+
+def _batched(name, seed_index, n_pairs, ref_bases, n_sampler, cands_sampler, ratio_lo, ratio_hi,
+             meta=None) -> Batch:
+    rng = rng_for(seed_index)
+    model = pore_model(rng)
+    bases = random_bases(rng, ref_bases)
+    r = expected_levels(bases, model)
+    L = len(r)
+    reads, pairs = [], []
+    while len(pairs) < n_pairs:
+        n = int(n_sampler(rng))
+        k = min(int(cands_sampler(rng)), n_pairs - len(pairs))
+        start = int(rng.integers(0, L - 4 * n))
+        ev, span = read_events(rng, r, start, n_events=n)
+        ri = len(reads)
+        reads.append(ev)
+        for c in range(k):
+            m = int(np.floor(n * rng.uniform(ratio_lo, ratio_hi)))
+            m = min(m, L)
+            if c == 0:
+                pairs.append((ri, _true_region(rng, start, span, m, L), m, True))
+            else:
+                pairs.append((ri, int(rng.integers(0, L - m + 1)), m, False))
+    return _pack(name, reads, pairs, r, dict(meta or {}, reference_bases=ref_bases))
+
+
+def config1(n_pairs: int = 4096) -> Batch:
+    """Plain batched: n ~ U[200, 2000], m = floor(n * U[1.2, 2.0]), 10
+    candidates per read (1 true, 9 decoys: about 90% decoys)."""
+    return _batched("config1_plain_batched", 1, n_pairs, 1_000_000,
+                    lambda g: g.integers(200, 2001), lambda g: 10, 1.2, 2.0, {"config": 1})
+
+
+def config2(n_pairs: int = 100_000) -> Batch:
+    """Uneven batch: n = clip(round(LogNormal(ln 1500, 0.6)), 100, 8000),
+    m = floor(n * U[1.2, 3.0]), 1-50 candidates per read, 50M-base reference."""
+    def n_samp(g):
+        return int(np.clip(np.round(g.lognormal(np.log(1500.0), 0.6)), 100, 8000))
+    return _batched("config2_uneven_batch", 2, n_pairs, 50_000_000, n_samp,
+                    lambda g: g.integers(1, 51), 1.2, 3.0, {"config": 2})
+
+
+def config4(n_pairs: int = 1024, n: int = 10_000, m: int = 20_000) -> Batch:
+    """Long-problem stress: n = 10,000 events against m = 20,000 levels; every
+    read has one candidate, true for even reads and a decoy for odd ones."""
+    rng = rng_for(4)
+    model = pore_model(rng)
+    bases = random_bases(rng, 10_000_000)
+    r = expected_levels(bases, model)
+    L = len(r)
+    reads, pairs = [], []
+    for k in range(n_pairs):
+        start = int(rng.integers(0, L - 4 * n))
+        ev, span = read_events(rng, r, start, n_events=n)
+        reads.append(ev)
+        if k % 2 == 0:
+            pairs.append((k, _true_region(rng, start, span, m, L), m, True))
+        else:
+            pairs.append((k, int(rng.integers(0, L - m + 1)), m, False))
+    return _pack("config4_long_stress", reads, pairs, r, {"config": 4, "reference_bases": len(bases)})
+
+
+def random_pairs(rng, n_pairs, n_range, m_range, value_fn=None, share_query=False) -> Batch:
+    """Unstructured pairs for edge-case tests: lengths uniform in the inclusive
+    ranges, values from value_fn(rng, size) (default N(0, 1) float32)."""
+    if value_fn is None:
+        def value_fn(g, size):
+            return g.standard_normal(size).astype(np.float32)
+    ns = rng.integers(n_range[0], n_range[1] + 1, size=n_pairs)
+    ms = rng.integers(m_range[0], m_range[1] + 1, size=n_pairs)
+    reads = [value_fn(rng, int(ns[0] if share_query else x)) for x in (ns[:1] if share_query else ns)]
+    r = value_fn(rng, int(ms.sum()) + 1)
+    pairs = []
+    off = 0
+    for p in range(n_pairs):
+        pairs.append((0 if share_query else p, off, int(ms[p]), p == 0))
+        off += int(ms[p])
+    return _pack("random_pairs", reads, pairs, r, {})
+
+
+def dyadic_values(g, size, lo=-8.0, hi=8.0, step=0.25):
+    """Multiples of `step` in [lo, hi]: every partial sum of a short path is
+    exact in float, so float and double arithmetic agree exactly."""
+    k = g.integers(int(lo / step), int(hi / step) + 1, size=size)
+    return (k * step).astype(np.float32)
+
+
+# ---- serving workload (Read Until): reads streamed in 400-event chunks ----
+
+@dataclass
+class ServingRead:
+    arrival: float          # seconds since the start of the run
+    events: np.ndarray      # float32, all chunks concatenated
+    r_off: np.ndarray       # int64 per candidate
+    r_len: np.ndarray       # int32 per candidate
+    true_cand: int
+
+
+@dataclass
+class ServingWorkload:
+    r: np.ndarray
+    reads: list
+    chunk: int
+    period: float           # seconds between consecutive chunks of a read
+    rate: float
+
+
+def serving_workload(n_reads: int, rate: float = 2000.0, chunk: int = 400, max_chunks: int = 10,
+                     max_cands: int = 50, ref_bases: int = 10_000_000, period: float = 1.0,
+                     seed_index: int = 3) -> ServingWorkload:
+    """Poisson arrivals at `rate` reads/s; each read has U{1..max_chunks}
+    chunks of `chunk` events and U{1..max_cands} candidates fixed at its first
+    chunk, with m = floor(chunk * chunks * U[1.2, 3.0]) levels each."""
+    rng = rng_for(seed_index)
+    model = pore_model(rng)
+    bases = random_bases(rng, ref_bases)
+    r = expected_levels(bases, model)
+    L = len(r)
+    t = 0.0
+    reads = []
+    for _ in range(n_reads):
+        t += float(rng.exponential(1.0 / rate))
+        chunks = int(rng.integers(1, max_chunks + 1))
+        n = chunks * chunk
+        start = int(rng.integers(0, L - 4 * n))
+        ev, span = read_events(rng, r, start, n_events=n)
+        k = int(rng.integers(1, max_cands + 1))
+        offs, lens = [], []
+        for c in range(k):
+            m = min(int(np.floor(n * rng.uniform(1.2, 3.0))), L)
+            offs.append(_true_region(rng, start, span, m, L) if c == 0 else int(rng.integers(0, L - m + 1)))
+            lens.append(m)
+        reads.append(ServingRead(t, ev, np.array(offs, np.int64), np.array(lens, np.int32), 0))
+    return ServingWorkload(r, reads, chunk, period, rate)
