@@ -1,0 +1,212 @@
+/*
+ * rawalign.h -- C ABI of librawalign.so, batched subsequence dynamic time
+ * warping (DTW) for raw nanopore signal alignment on AMD MI355X (gfx950).
+ *
+ * Method: RawAlign (arXiv 2310.05037).  The alignment step (Sec. 2.1.3)
+ * re-evaluates every candidate region left by chaining with DTW (Sec. 2.2):
+ * a table whose cells add the numerical difference of a read event and a
+ * reference level (no fixed indel penalty) to the smallest of the north,
+ * north-west and west neighbours.  The read is aligned whole against a region
+ * that is longer than it, so the path may start and end anywhere in the
+ * region (subsequence DTW):
+ *
+ *   c(i,j)  = |q_i - r_j|,        D(-1,j) = 0 (j >= -1),  D(i,-1) = +inf,
+ *   D(i,j)  = c(i,j) + min{ D(i-1,j-1), D(i-1,j), D(i,j-1) },
+ *   C_DTW   = min_j D(n-1,j),     end = smallest j attaining C_DTW.
+ *
+ * All arithmetic is IEEE float32; every cell is one rounded subtraction, an
+ * exact |.|, an exact min and one rounded addition, so results do not depend
+ * on the order in which cells are evaluated (every kernel variant and every
+ * launch configuration returns bit-identical scores and ends).
+ *
+ * Conventions shared by all entry points
+ *  - Pointers documented as "device" must point to device memory (hipMalloc,
+ *    torch CUDA tensors); "host" pointers to host memory.  The caller owns all
+ *    memory passed in; the library never frees it.  Inputs must stay valid
+ *    and unmodified until the stream reaches the call.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued asynchronously on it; the host never reads device data, so a
+ *    call returns before the GPU has finished.
+ *  - Pair layout: pair p aligns q[q_off[p] .. q_off[p]+q_len[p]) against
+ *    r[r_off[p] .. r_off[p]+r_len[p]).  Offsets are in elements.  Pairs may
+ *    share query slices (one read, many candidates) and region slices may
+ *    alias one reference-level array; nothing is copied.
+ *  - Return value: RAWALIGN_OK (0) or a negative error code; the message of
+ *    the last error on the calling thread is rawalign_last_error().  Argument
+ *    errors are detected on the host before anything is enqueued.
+ *  - Per-pair conditions that only the device can see (it alone reads the
+ *    offset and length arrays) give sentinel outputs, never faults:
+ *      q_len == 0                   -> score 0,    end -1
+ *      r_len == 0 (and q_len > 0)   -> score +inf, end -1
+ *      negative length, or a slice outside [0, q_size) / [0, r_size),
+ *      or r_len > RAWALIGN_MAX_REGION, or q_len > RAWALIGN_MAX_QUERY
+ *                                     -> score NaN, end -2 (pair skipped)
+ */
+#ifndef RAWALIGN_H
+#define RAWALIGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAWALIGN_OK 0
+#define RAWALIGN_EINVAL (-1)      /* bad argument (null pointer, negative count, bad option) */
+#define RAWALIGN_EHIP (-2)        /* HIP runtime or launch error; message keeps hipGetErrorString */
+#define RAWALIGN_ENOMEM (-3)      /* internal scratch allocation failed */
+#define RAWALIGN_ENODEV (-4)      /* no usable gfx950 device */
+
+/* Longest region (levels) a pair may have: 8 cooperating waves x 64 lanes x
+ * 64 columns per lane. */
+#define RAWALIGN_MAX_REGION 32768
+/* Longest query (events) a pair may have. */
+#define RAWALIGN_MAX_QUERY (1 << 28)
+
+/* Scheduling modes of rawalign_dtw_batch_ex. */
+#define RAWALIGN_MODE_PLAIN 0       /* one workgroup per pair, input order, fixed split */
+#define RAWALIGN_MODE_PERSISTENT 1  /* persistent grid, atomic work queue, longest pairs first */
+
+/* Kernels for pairs above the short/long split. */
+#define RAWALIGN_LONG_STRIPED 0     /* waves own column stripes, edges through LDS rings */
+#define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup sweeps anti-diagonals, 3 diagonals in LDS */
+
+/* opts.flags */
+#define RAWALIGN_FLAG_TIMING 1      /* record hipEvents around every kernel (rawalign_last_timing) */
+
+typedef struct rawalign_opts {
+    int32_t mode;          /* RAWALIGN_MODE_*; */
+    int32_t long_kernel;   /* RAWALIGN_LONG_*; */
+    int32_t short_max;     /* pairs with r_len <= short_max run on one wave each (<= 4096);
+                              longer pairs run on a cooperating workgroup.  0 = default */
+    int32_t coop_waves;    /* waves per workgroup for long pairs, 2..8; 0 = default */
+    int32_t waves_per_cu;  /* persistent grid size per CU (0 = occupancy limit) */
+    int32_t flags;         /* RAWALIGN_FLAG_* */
+} rawalign_opts;
+
+/* Fill `opts` with the library defaults (persistent mode, striped long
+ * kernel, short_max 4096, 4 cooperating waves).  Returns RAWALIGN_OK. */
+int rawalign_opts_default(rawalign_opts *opts);
+
+/*
+ * Plain batched subsequence DTW (Sec. 2.2): one launch of the short-pair
+ * kernel with one wavefront per pair in input order and one launch of the
+ * long-pair kernel for pairs with r_len > 4096.  This is the baseline.
+ *
+ *   q, r          device, float32 read events / reference levels
+ *   q_size, r_size  number of elements in q and r (bounds for the slices)
+ *   q_off, r_off  device, int64 per pair;  q_len, r_len  device, int32 per pair
+ *   n_pairs       number of pairs (>= 0; 0 returns at once)
+ *   out_score     device, float32 per pair: C_DTW (lower is better)
+ *   out_end       device, int32 per pair: 0-based index j into the pair's
+ *                 region where the best path ends (smallest on ties)
+ *
+ * Internal scratch (planning lists, queue counters) is allocated by the
+ * library per (device, stream) on first use, grown when a larger batch
+ * arrives and kept until process exit.  Calls on one stream are ordered by
+ * the stream; calls on different streams use different scratch.  Growing the
+ * scratch calls hipMalloc, so a call that may be captured into a HIP graph
+ * must follow an uncaptured call of at least the same n_pairs on that stream.
+ */
+int rawalign_dtw_batch(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                       int64_t n_pairs, float *out_score, int32_t *out_end, void *stream);
+
+/*
+ * Batched subsequence DTW with scheduling options (Sec. 2.2; systems layer):
+ * `opts` NULL means the tuned settings for this device if a tuning cache was
+ * loaded (rawalign_autotune / rawalign_load_tuning), else the defaults.
+ * Persistent mode orders pairs by cell count, longest first, and lets a
+ * device-sized grid pull them from an atomic queue.  Arguments as in
+ * rawalign_dtw_batch; results are bit-identical to it.
+ */
+int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                          const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                          int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                          const rawalign_opts *opts);
+
+/*
+ * Streaming extension for Read Until (Sec. 1, Sec. 3.1.2: reads arrive in
+ * chunks and a decision is taken after each one).  Job k continues the
+ * alignment of one (read, candidate) pair by the events of a new chunk:
+ * rows[row_off[k] .. +r_len[k]) holds the last DTW row of the events seen so
+ * far (D(N-1, j) for every region level j) and is used as row -1 of the new
+ * chunk (its corner D(-1,-1) is +inf); first_chunk[k] != 0 means no events
+ * were seen yet and row -1 is all zero (the stored row is not read).  On
+ * return the row holds the last row after the chunk, and out_score/out_end
+ * are C_DTW and end of the whole prefix seen so far, identical to aligning
+ * the concatenated prefix at once.
+ *
+ *   q, q_size, q_off, q_len  device, the chunk events of every job
+ *   r, r_size, r_off, r_len  device, the candidate regions
+ *   rows, rows_size          device float32 arena (caller-owned) and its size
+ *   row_off                  device int64 per job, start of the job's row
+ *   first_chunk              device uint8 per job
+ *   n_jobs, out_score, out_end, stream  as above
+ * Jobs must not share a row.  A job whose row slice leaves [0, rows_size)
+ * gets score NaN, end -2 and its row is untouched.  q_len == 0 leaves the
+ * row unchanged and reports the stored row's minimum.
+ */
+int rawalign_dtw_extend(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                        const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                        float *rows, int64_t rows_size, const int64_t *row_off,
+                        const uint8_t *first_chunk, int64_t n_jobs,
+                        float *out_score, int32_t *out_end, void *stream, const rawalign_opts *opts);
+
+/*
+ * Mapping decision (Sec. 2.3): for read k with candidate pairs
+ * cand_off[k] .. cand_off[k]+cand_cnt[k]-1 and n_events[k] aligned events,
+ * Score = b_match * N_Read - C_DTW (double precision, from the float C_DTW);
+ * the highest score wins (smallest pair index on ties) and the read is mapped
+ * iff that score >= threshold.  The paper's defaults are b_match = 0.4 and
+ * threshold = 20 (Sec. 3.1.5).
+ *   score                     device float32 per pair (C_DTW from a DTW call)
+ *   cand_off                  device int64 per read;  cand_cnt, n_events device int32 per read
+ *   out_best                  device int32 per read: winning pair index, -1 if no candidates
+ *   out_score                 device float64 per read: winning Score, -inf if none
+ *   out_mapped                device uint8 per read
+ * A read whose candidate range leaves [0, n_pairs) gets out_best -2, score
+ * NaN, not mapped.
+ */
+int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
+                    const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
+                    int32_t *out_best, double *out_score, uint8_t *out_mapped, void *stream);
+
+/*
+ * Autotuner: times candidate settings (short/long split, waves per
+ * cooperating workgroup, persistent grid size) on the caller's device batch
+ * (same layout as rawalign_dtw_batch; out_score/out_end are scratch outputs)
+ * and keeps the fastest as this device's tuned setting.  If cache_path is not
+ * NULL the result is also written there as JSON keyed by device name, gfx
+ * architecture and library version.  `best` (host, may be NULL) receives it.
+ * Synchronises `stream`.
+ */
+int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                      const char *cache_path, rawalign_opts *best);
+
+/* Load a tuning cache written by rawalign_autotune; entries for other
+ * devices or library versions are ignored (returns RAWALIGN_EINVAL then). */
+int rawalign_load_tuning(const char *cache_path, rawalign_opts *out);
+
+/* Per-kernel timing of the last call made with RAWALIGN_FLAG_TIMING. */
+typedef struct rawalign_timing {
+    float plan_ms;    /* ordering / routing kernels */
+    float short_ms;   /* short-pair kernel */
+    float long_ms;    /* long-pair kernel */
+    float total_ms;   /* first to last event of the call */
+} rawalign_timing;
+int rawalign_last_timing(rawalign_timing *out);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *rawalign_last_error(void);
+
+/* Library version string. */
+const char *rawalign_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAWALIGN_H */

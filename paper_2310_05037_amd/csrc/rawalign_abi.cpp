@@ -1,0 +1,487 @@
+// rawalign_abi.cpp -- the C ABI of librawalign.so (declared in include/rawalign.h):
+// argument checks, per-stream scratch, launch order, tuning cache, timing.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "rawalign.h"
+
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.1.0"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(RAWALIGN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DeviceInfo {
+    int cus = 0;
+    std::string name;
+    std::string arch;
+    bool ok = false;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_dev;
+std::map<int, rawalign_opts> g_tuned;   // device -> tuned settings
+
+struct StreamScratch {
+    int32_t *words = nullptr;   // hist | counts | queue
+    int32_t *list = nullptr;
+    int64_t capacity = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
+
+struct TimingRecord {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool valid = false;
+};
+TimingRecord g_last_timing;
+
+int device_info(int &dev, DeviceInfo &info) {
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        DeviceInfo d;
+        d.cus = prop.multiProcessorCount;
+        d.name = prop.name;
+        d.arch = prop.gcnArchName;
+        d.ok = d.arch.rfind("gfx950", 0) == 0;
+        it = g_dev.emplace(dev, d).first;
+    }
+    info = it->second;
+    if (!info.ok) return fail(RAWALIGN_ENODEV, "librawalign is built for gfx950; device " + std::to_string(dev) +
+                                                   " is " + info.arch);
+    return RAWALIGN_OK;
+}
+
+int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, bool timing, StreamScratch *&out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    StreamScratch &s = g_scratch[{dev, stream}];
+    if (!s.words) {
+        const size_t words = (size_t)ra::kNumRoutes * ra::kBuckets + 2 * ra::kNumRoutes;
+        hipError_t e = hipMalloc((void **)&s.words, words * sizeof(int32_t));
+        if (e != hipSuccess) {
+            s.words = nullptr;
+            return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+        }
+    }
+    if (s.capacity < n_pairs) {
+        int64_t cap = s.capacity ? s.capacity : 1024;
+        while (cap < n_pairs) cap *= 2;
+        if (s.list) (void)hipFree(s.list);
+        s.list = nullptr;
+        s.capacity = 0;
+        hipError_t e = hipMalloc((void **)&s.list, (size_t)cap * ra::kNumRoutes * sizeof(int32_t));
+        if (e != hipSuccess) {
+            s.list = nullptr;
+            return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+        }
+        s.capacity = cap;
+    }
+    if (timing && !s.ev[0]) {
+        for (auto &ev : s.ev) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+    }
+    out = &s;
+    return RAWALIGN_OK;
+}
+
+ra::PlanScratch plan_view(StreamScratch &s) {
+    ra::PlanScratch p;
+    p.hist = s.words;
+    p.counts = s.words + ra::kNumRoutes * ra::kBuckets;
+    p.queue = p.counts + ra::kNumRoutes;
+    p.list = s.list;
+    p.capacity = s.capacity;
+    return p;
+}
+
+int check_opts(const rawalign_opts &o) {
+    if (o.mode != RAWALIGN_MODE_PLAIN && o.mode != RAWALIGN_MODE_PERSISTENT)
+        return fail(RAWALIGN_EINVAL, "opts.mode must be RAWALIGN_MODE_PLAIN or RAWALIGN_MODE_PERSISTENT");
+    if (o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
+        return fail(RAWALIGN_EINVAL, "opts.long_kernel RAWALIGN_LONG_ANTIDIAG is not available in this build");
+    if (o.long_kernel != RAWALIGN_LONG_STRIPED)
+        return fail(RAWALIGN_EINVAL, "opts.long_kernel must be RAWALIGN_LONG_STRIPED or RAWALIGN_LONG_ANTIDIAG");
+    if (o.short_max < 0 || o.short_max > ra::kShortMaxRegion)
+        return fail(RAWALIGN_EINVAL, "opts.short_max must be in [0, 4096]");
+    if (o.coop_waves != 0 && (o.coop_waves < 2 || o.coop_waves > ra::kMaxCoopWaves))
+        return fail(RAWALIGN_EINVAL, "opts.coop_waves must be 0 or in [2, 8]");
+    if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
+        return fail(RAWALIGN_EINVAL, "opts.waves_per_cu must be in [0, 64]");
+    return RAWALIGN_OK;
+}
+
+void defaults(rawalign_opts &o) {
+    o.mode = RAWALIGN_MODE_PERSISTENT;
+    o.long_kernel = RAWALIGN_LONG_STRIPED;
+    o.short_max = ra::kShortMaxRegion;
+    o.coop_waves = 4;
+    o.waves_per_cu = 0;
+    o.flags = 0;
+}
+
+struct Call {
+    const float *q;
+    int64_t q_size;
+    const int64_t *q_off;
+    const int32_t *q_len;
+    const float *r;
+    int64_t r_size;
+    const int64_t *r_off;
+    const int32_t *r_len;
+    int64_t n_pairs;
+    float *out_score;
+    int32_t *out_end;
+    float *rows;
+    int64_t rows_size;
+    const int64_t *row_off;
+    const uint8_t *first_chunk;
+    hipStream_t stream;
+};
+
+int check_call(const Call &c) {
+    if (c.n_pairs < 0) return fail(RAWALIGN_EINVAL, "n_pairs must be >= 0");
+    if (c.n_pairs >= (int64_t)1 << 31) return fail(RAWALIGN_EINVAL, "n_pairs must be < 2^31");
+    if (c.q_size < 0 || c.r_size < 0) return fail(RAWALIGN_EINVAL, "q_size and r_size must be >= 0");
+    if (c.q_size >= ((int64_t)1 << 40) || c.r_size >= ((int64_t)1 << 40))
+        return fail(RAWALIGN_EINVAL, "q_size and r_size must be < 2^40");
+    if (c.n_pairs == 0) return RAWALIGN_OK;
+    if (!c.q_off || !c.q_len || !c.r_off || !c.r_len || !c.out_score || !c.out_end)
+        return fail(RAWALIGN_EINVAL, "null pointer argument");
+    if ((c.q_size > 0 && !c.q) || (c.r_size > 0 && !c.r)) return fail(RAWALIGN_EINVAL, "null data pointer");
+    if (c.rows && (!c.row_off || !c.first_chunk || c.rows_size < 0))
+        return fail(RAWALIGN_EINVAL, "extend: rows, row_off and first_chunk are required");
+    return RAWALIGN_OK;
+}
+
+int run(const Call &c, const rawalign_opts &o) {
+    int rc = check_call(c);
+    if (rc) return rc;
+    rc = check_opts(o);
+    if (rc) return rc;
+    if (c.n_pairs == 0) return RAWALIGN_OK;
+    int dev = 0;
+    DeviceInfo info;
+    rc = device_info(dev, info);
+    if (rc) return rc;
+    const bool timing = (o.flags & RAWALIGN_FLAG_TIMING) != 0;
+    StreamScratch *s = nullptr;
+    rc = get_scratch(dev, c.stream, c.n_pairs, timing, s);
+    if (rc) return rc;
+
+    ra::PairArrays a;
+    a.q = c.q;
+    a.q_size = c.q_size;
+    a.q_off = c.q_off;
+    a.q_len = c.q_len;
+    a.r = c.r;
+    a.r_size = c.r_size;
+    a.r_off = c.r_off;
+    a.r_len = c.r_len;
+    a.out_score = c.out_score;
+    a.out_end = c.out_end;
+    a.rows = c.rows;
+    a.rows_size = c.rows_size;
+    a.row_off = c.row_off;
+    a.first_chunk = c.first_chunk;
+
+    ra::LaunchCfg cfg;
+    cfg.short_max = o.short_max;
+    cfg.coop_waves = o.coop_waves ? o.coop_waves : 4;
+    cfg.persistent = o.mode == RAWALIGN_MODE_PERSISTENT;
+    cfg.antidiag = o.long_kernel == RAWALIGN_LONG_ANTIDIAG;
+    const bool ext = c.rows != nullptr;
+    cfg.short_lo_grid = info.cus * (o.waves_per_cu ? o.waves_per_cu : ra::short_blocks_per_cu(ext, false));
+    cfg.short_hi_grid = info.cus * (o.waves_per_cu ? o.waves_per_cu : ra::short_blocks_per_cu(ext, true));
+    cfg.long_grid = info.cus * ra::long_blocks_per_cu(cfg.coop_waves, ext, cfg.antidiag);
+    cfg.huge_grid = info.cus * ra::long_blocks_per_cu(ra::kMaxCoopWaves, ext, cfg.antidiag);
+
+    const ra::PlanScratch ps = plan_view(*s);
+    hipError_t e;
+    if (timing) {
+        e = hipEventRecord(s->ev[0], c.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "plan kernels");
+    if (timing) (void)hipEventRecord(s->ev[1], c.stream);
+    // Longest pairs first: they bound the makespan.
+    e = ra::launch_huge(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "long-pair kernel (8 waves)");
+    e = ra::launch_long(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "long-pair kernel");
+    if (timing) (void)hipEventRecord(s->ev[2], c.stream);
+    e = ra::launch_short_hi(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "short-pair kernel (33-64 columns per lane)");
+    e = ra::launch_short_lo(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "short-pair kernel (4-32 columns per lane)");
+    if (timing) {
+        (void)hipEventRecord(s->ev[3], c.stream);
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int i = 0; i < 4; ++i) g_last_timing.ev[i] = s->ev[i];
+        g_last_timing.valid = true;
+    }
+    return RAWALIGN_OK;
+}
+
+rawalign_opts effective_opts(const rawalign_opts *opts) {
+    rawalign_opts o;
+    if (opts) return *opts;
+    defaults(o);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tuned.find(dev);
+        if (it != g_tuned.end()) o = it->second;
+    }
+    return o;
+}
+
+std::string json_escape(const std::string &s) {
+    std::string o;
+    for (char ch : s) {
+        if (ch == '"' || ch == '\\') o += '\\';
+        o += ch;
+    }
+    return o;
+}
+
+// Minimal reader for the flat JSON objects this library writes.
+bool json_get(const std::string &doc, const std::string &key, std::string &val) {
+    const std::string pat = "\"" + key + "\"";
+    size_t k = doc.find(pat);
+    if (k == std::string::npos) return false;
+    k = doc.find(':', k + pat.size());
+    if (k == std::string::npos) return false;
+    ++k;
+    while (k < doc.size() && (doc[k] == ' ' || doc[k] == '\t')) ++k;
+    if (k < doc.size() && doc[k] == '"') {
+        size_t e = doc.find('"', k + 1);
+        if (e == std::string::npos) return false;
+        val = doc.substr(k + 1, e - k - 1);
+        return true;
+    }
+    size_t e = doc.find_first_of(",}\n", k);
+    val = doc.substr(k, e == std::string::npos ? std::string::npos : e - k);
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rawalign_opts_default(rawalign_opts *opts) {
+    if (!opts) return fail(RAWALIGN_EINVAL, "opts is null");
+    defaults(*opts);
+    return RAWALIGN_OK;
+}
+
+int rawalign_dtw_batch(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                       int64_t n_pairs, float *out_score, int32_t *out_end, void *stream) {
+    rawalign_opts o;
+    defaults(o);
+    o.mode = RAWALIGN_MODE_PLAIN;
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
+    return run(c, o);
+}
+
+int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                          const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                          int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                          const rawalign_opts *opts) {
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
+    return run(c, effective_opts(opts));
+}
+
+int rawalign_dtw_extend(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                        const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                        float *rows, int64_t rows_size, const int64_t *row_off,
+                        const uint8_t *first_chunk, int64_t n_jobs,
+                        float *out_score, int32_t *out_end, void *stream, const rawalign_opts *opts) {
+    if (n_jobs > 0 && !rows) return fail(RAWALIGN_EINVAL, "extend: rows is null");
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_jobs, out_score, out_end,
+           rows, rows_size, row_off, first_chunk, (hipStream_t)stream};
+    return run(c, effective_opts(opts));
+}
+
+int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
+                    const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
+                    int32_t *out_best, double *out_score, uint8_t *out_mapped, void *stream) {
+    if (n_reads < 0 || n_pairs < 0) return fail(RAWALIGN_EINVAL, "n_reads and n_pairs must be >= 0");
+    if (n_reads == 0) return RAWALIGN_OK;
+    if (!cand_off || !cand_cnt || !n_events || !out_best || !out_score || !out_mapped ||
+        (n_pairs > 0 && !score))
+        return fail(RAWALIGN_EINVAL, "null pointer argument");
+    if (!std::isfinite(b_match) || std::isnan(threshold))
+        return fail(RAWALIGN_EINVAL, "b_match must be finite and threshold not NaN");
+    int dev = 0;
+    DeviceInfo info;
+    int rc = device_info(dev, info);
+    if (rc) return rc;
+    hipError_t e = ra::launch_decide(score, n_pairs, cand_off, cand_cnt, n_events, n_reads, b_match, threshold,
+                                     out_best, out_score, out_mapped, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "decide kernel");
+    return RAWALIGN_OK;
+}
+
+int rawalign_last_timing(rawalign_timing *out) {
+    if (!out) return fail(RAWALIGN_EINVAL, "out is null");
+    TimingRecord t;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        t = g_last_timing;
+    }
+    if (!t.valid) return fail(RAWALIGN_EINVAL, "no call with RAWALIGN_FLAG_TIMING yet");
+    hipError_t e = hipEventSynchronize(t.ev[3]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms[3];
+    for (int i = 0; i < 3; ++i) {
+        e = hipEventElapsedTime(&ms[i], t.ev[i], t.ev[i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    }
+    out->plan_ms = ms[0];
+    out->long_ms = ms[1];
+    out->short_ms = ms[2];
+    out->total_ms = ms[0] + ms[1] + ms[2];
+    return RAWALIGN_OK;
+}
+
+int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                      const char *cache_path, rawalign_opts *best_out) {
+    int dev = 0;
+    DeviceInfo info;
+    int rc = device_info(dev, info);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, st};
+    rc = check_call(c);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RAWALIGN_EHIP, "hipEventCreate");
+    std::vector<rawalign_opts> cands;
+    const int splits[] = {2048, 3072, 4096};
+    const int coop[] = {2, 4, 8};
+    for (int sm : splits)
+        for (int cw : coop) {
+            rawalign_opts o;
+            defaults(o);
+            o.short_max = sm;
+            o.coop_waves = cw;
+            cands.push_back(o);
+        }
+    float best_ms = 1e30f;
+    rawalign_opts best;
+    defaults(best);
+    for (const rawalign_opts &o : cands) {
+        rc = run(c, o);   // warm-up (also grows scratch)
+        if (rc) break;
+        float tot = 0.0f;
+        const int reps = 3;
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < reps && !rc; ++i) rc = run(c, o);
+        (void)hipEventRecord(e1, st);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(RAWALIGN_EHIP, "hipEventSynchronize");
+            break;
+        }
+        (void)hipEventElapsedTime(&tot, e0, e1);
+        if (tot / reps < best_ms) {
+            best_ms = tot / reps;
+            best = o;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[dev] = best;
+    }
+    if (best_out) *best_out = best;
+    if (cache_path) {
+        std::ofstream f(cache_path);
+        if (!f) return fail(RAWALIGN_EINVAL, std::string("cannot write ") + cache_path);
+        f << "{\"device\": \"" << json_escape(info.name) << "\", \"arch\": \"" << json_escape(info.arch)
+          << "\", \"version\": \"" << RAWALIGN_VERSION_STRING << "\", \"mode\": " << best.mode
+          << ", \"long_kernel\": " << best.long_kernel << ", \"short_max\": " << best.short_max
+          << ", \"coop_waves\": " << best.coop_waves << ", \"waves_per_cu\": " << best.waves_per_cu
+          << ", \"ms\": " << best_ms << "}\n";
+    }
+    return RAWALIGN_OK;
+}
+
+int rawalign_load_tuning(const char *cache_path, rawalign_opts *out) {
+    if (!cache_path) return fail(RAWALIGN_EINVAL, "cache_path is null");
+    std::ifstream f(cache_path);
+    if (!f) return fail(RAWALIGN_EINVAL, std::string("cannot read ") + cache_path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string doc = ss.str();
+    int dev = 0;
+    DeviceInfo info;
+    int rc = device_info(dev, info);
+    if (rc) return rc;
+    std::string v;
+    if (!json_get(doc, "arch", v) || v != info.arch) return fail(RAWALIGN_EINVAL, "tuning cache is for another device");
+    if (!json_get(doc, "device", v) || v != info.name) return fail(RAWALIGN_EINVAL, "tuning cache is for another device");
+    if (!json_get(doc, "version", v) || v != RAWALIGN_VERSION_STRING)
+        return fail(RAWALIGN_EINVAL, "tuning cache is for another library version");
+    rawalign_opts o;
+    defaults(o);
+    int32_t *fields[] = {&o.mode, &o.long_kernel, &o.short_max, &o.coop_waves, &o.waves_per_cu};
+    const char *names[] = {"mode", "long_kernel", "short_max", "coop_waves", "waves_per_cu"};
+    for (int i = 0; i < 5; ++i) {
+        if (!json_get(doc, names[i], v)) return fail(RAWALIGN_EINVAL, std::string("tuning cache lacks ") + names[i]);
+        *fields[i] = (int32_t)std::strtol(v.c_str(), nullptr, 10);
+    }
+    rc = check_opts(o);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[dev] = o;
+    }
+    if (out) *out = o;
+    return RAWALIGN_OK;
+}
+
+const char *rawalign_last_error(void) { return g_err.c_str(); }
+
+const char *rawalign_version(void) { return RAWALIGN_VERSION_STRING; }
+
+}  // extern "C"

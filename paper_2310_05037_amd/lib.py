@@ -1,0 +1,240 @@
+"""ctypes binding of librawalign.so (C ABI in include/rawalign.h).
+
+Argument marshalling only: every entry point takes torch CUDA tensors, checks
+their device, dtype and contiguity on the host, and passes raw device
+pointers plus the current HIP stream to the library function of the same
+name.  All computation happens in the library's HIP kernels; there is no
+fallback.  If the library is missing, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librawalign.so")
+
+RAWALIGN_OK = 0
+RAWALIGN_EINVAL = -1
+RAWALIGN_EHIP = -2
+RAWALIGN_ENOMEM = -3
+RAWALIGN_ENODEV = -4
+RAWALIGN_MAX_REGION = 32768
+MODE_PLAIN = 0
+MODE_PERSISTENT = 1
+LONG_STRIPED = 0
+LONG_ANTIDIAG = 1
+FLAG_TIMING = 1
+
+# Every symbol include/rawalign.h declares.
+EXPORTS = (
+    "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
+    "rawalign_decide", "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing",
+    "rawalign_last_error", "rawalign_version",
+)
+
+
+class RawAlignError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"librawalign error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("long_kernel", ctypes.c_int32), ("short_max", ctypes.c_int32),
+                ("coop_waves", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("plan_ms", ctypes.c_float), ("short_ms", ctypes.c_float), ("long_ms", ctypes.c_float),
+                ("total_ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librawalign.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    pair_args = [vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]
+    L.rawalign_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    L.rawalign_dtw_batch.argtypes = pair_args
+    L.rawalign_dtw_batch_ex.argtypes = pair_args + [ctypes.POINTER(Opts)]
+    L.rawalign_dtw_extend.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp,
+                                      ctypes.POINTER(Opts)]
+    L.rawalign_decide.argtypes = [vp, i64, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp]
+    L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
+    L.rawalign_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts)]
+    L.rawalign_last_timing.argtypes = [ctypes.POINTER(Timing)]
+    L.rawalign_last_error.restype = ctypes.c_char_p
+    L.rawalign_last_error.argtypes = []
+    L.rawalign_version.restype = ctypes.c_char_p
+    L.rawalign_version.argtypes = []
+    for name in EXPORTS:
+        if name not in ("rawalign_last_error", "rawalign_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != RAWALIGN_OK:
+        raise RawAlignError(rc, load().rawalign_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end):
+    import torch
+    n = q_off.numel()
+    for t, nm in ((q_len, "q_len"), (r_off, "r_off"), (r_len, "r_len"), (out_score, "out_score"),
+                  (out_end, "out_end")):
+        if t.numel() != n:
+            raise ValueError(f"{nm} has {t.numel()} elements, expected {n}")
+    return [_dev(q, torch.float32, "q"), q.numel(), _dev(q_off, torch.int64, "q_off"),
+            _dev(q_len, torch.int32, "q_len"), _dev(r, torch.float32, "r"), r.numel(),
+            _dev(r_off, torch.int64, "r_off"), _dev(r_len, torch.int32, "r_len"), n,
+            _dev(out_score, torch.float32, "out_score"), _dev(out_end, torch.int32, "out_end")]
+
+
+def opts_default() -> Opts:
+    o = Opts()
+    _check(load().rawalign_opts_default(ctypes.byref(o)))
+    return o
+
+
+def make_opts(**kw) -> Opts:
+    o = opts_default()
+    for k, v in kw.items():
+        setattr(o, k, int(v))
+    return o
+
+
+def rawalign_dtw_batch(q, q_off, q_len, r, r_off, r_len, out_score, out_end, stream=None):
+    _check(load().rawalign_dtw_batch(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
+                                     _stream(stream)))
+
+
+def rawalign_dtw_batch_ex(q, q_off, q_len, r, r_off, r_len, out_score, out_end, opts=None, stream=None):
+    _check(load().rawalign_dtw_batch_ex(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
+                                        _stream(stream), None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_dtw_extend(q, q_off, q_len, r, r_off, r_len, rows, row_off, first_chunk, out_score, out_end,
+                        opts=None, stream=None):
+    import torch
+    a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
+    n = a[8]
+    if row_off.numel() != n or first_chunk.numel() != n:
+        raise ValueError("row_off and first_chunk need one entry per job")
+    _check(load().rawalign_dtw_extend(*a[:8], _dev(rows, torch.float32, "rows"), rows.numel(),
+                                      _dev(row_off, torch.int64, "row_off"),
+                                      _dev(first_chunk, torch.uint8, "first_chunk"), n, a[9], a[10],
+                                      _stream(stream), None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_decide(score, cand_off, cand_cnt, n_events, out_best, out_score, out_mapped,
+                    b_match=0.4, threshold=20.0, stream=None):
+    import torch
+    n_reads = cand_off.numel()
+    for t, nm in ((cand_cnt, "cand_cnt"), (n_events, "n_events"), (out_best, "out_best"),
+                  (out_score, "out_score"), (out_mapped, "out_mapped")):
+        if t.numel() != n_reads:
+            raise ValueError(f"{nm} has {t.numel()} elements, expected {n_reads}")
+    _check(load().rawalign_decide(_dev(score, torch.float32, "score"), score.numel(),
+                                  _dev(cand_off, torch.int64, "cand_off"), _dev(cand_cnt, torch.int32, "cand_cnt"),
+                                  _dev(n_events, torch.int32, "n_events"), n_reads, float(b_match),
+                                  float(threshold), _dev(out_best, torch.int32, "out_best"),
+                                  _dev(out_score, torch.float64, "out_score"),
+                                  _dev(out_mapped, torch.uint8, "out_mapped"), _stream(stream)))
+
+
+def rawalign_autotune(q, q_off, q_len, r, r_off, r_len, out_score, out_end, cache_path=None, stream=None) -> Opts:
+    best = Opts()
+    _check(load().rawalign_autotune(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
+                                    _stream(stream), None if cache_path is None else cache_path.encode(),
+                                    ctypes.byref(best)))
+    return best
+
+
+def rawalign_load_tuning(cache_path: str) -> Opts:
+    o = Opts()
+    _check(load().rawalign_load_tuning(cache_path.encode(), ctypes.byref(o)))
+    return o
+
+
+def rawalign_last_timing() -> Timing:
+    t = Timing()
+    _check(load().rawalign_last_timing(ctypes.byref(t)))
+    return t
+
+
+def rawalign_version() -> str:
+    return load().rawalign_version().decode()
+
+
+# ---- convenience: packed batches on the device --------------------------------
+
+class DeviceBatch:
+    """A workloads.Batch copied to device tensors, plus output buffers."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        self.batch = batch
+        self.q = torch.from_numpy(np.ascontiguousarray(batch.q)).to(device)
+        self.r = torch.from_numpy(np.ascontiguousarray(batch.r)).to(device)
+        self.q_off = torch.from_numpy(batch.q_off.astype(np.int64)).to(device)
+        self.q_len = torch.from_numpy(batch.q_len.astype(np.int32)).to(device)
+        self.r_off = torch.from_numpy(batch.r_off.astype(np.int64)).to(device)
+        self.r_len = torch.from_numpy(batch.r_len.astype(np.int32)).to(device)
+        n = batch.n_pairs
+        self.score = torch.empty(n, dtype=torch.float32, device=device)
+        self.end = torch.empty(n, dtype=torch.int32, device=device)
+
+    def args(self):
+        return (self.q, self.q_off, self.q_len, self.r, self.r_off, self.r_len, self.score, self.end)
+
+    def run(self, opts=None, plain=False, stream=None):
+        if plain:
+            rawalign_dtw_batch(*self.args(), stream=stream)
+        else:
+            rawalign_dtw_batch_ex(*self.args(), opts=opts, stream=stream)
+
+    def results(self):
+        import torch
+        torch.cuda.synchronize()
+        return self.score.cpu().numpy(), self.end.cpu().numpy()
+
+
+def dtw(batch, opts=None, plain=False):
+    """Align a workloads.Batch on the GPU -> (scores float32, ends int32) on the host."""
+    db = DeviceBatch(batch)
+    db.run(opts=opts, plain=plain)
+    return db.results()

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every entry point the header declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2310_05037_amd import lib
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2310_05037_amd import build
+        build.build()
+    return lib
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "rawalign.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(rawalign_\w+)\(", text, re.M)))
+
+
+def test_header_declarations_are_exported(L):
+    decl = _declared()
+    assert len(decl) >= 10
+    assert sorted(L.EXPORTS) == decl
+    so = L.load()
+    for name in decl:
+        assert hasattr(so, name), name
+
+
+def test_version_and_defaults(L):
+    assert L.rawalign_version().startswith("rawalign-mi355x")
+    o = L.opts_default()
+    assert o.mode == L.MODE_PERSISTENT and o.short_max == 4096 and o.coop_waves == 4
+
+
+def test_argument_errors_without_device(L):
+    so = L.load()
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    # negative pair count
+    rc = so.rawalign_dtw_batch(fake, 10, fake, fake, fake, 10, fake, fake, -1, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
+    # null offsets
+    rc = so.rawalign_dtw_batch(fake, 10, None, fake, fake, 10, fake, fake, 3, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"null" in so.rawalign_last_error()
+    # zero pairs: nothing to do, success
+    rc = so.rawalign_dtw_batch(None, 0, None, None, None, 0, None, None, 0, None, None, None)
+    assert rc == L.RAWALIGN_OK
+    # bad option values
+    o = L.opts_default()
+    o.mode = 9
+    rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"mode" in so.rawalign_last_error()
+    o = L.opts_default()
+    o.coop_waves = 16
+    rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"coop_waves" in so.rawalign_last_error()
+    # extend without a row arena
+    rc = so.rawalign_dtw_extend(fake, 10, fake, fake, fake, 10, fake, fake, None, 0, fake, fake, 2, fake, fake,
+                                None, None)
+    assert rc == L.RAWALIGN_EINVAL
+    # decide with a negative read count
+    rc = so.rawalign_decide(fake, 1, fake, fake, fake, -1, 0.4, 20.0, fake, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL
+
+
+def test_binding_rejects_host_tensors(L):
+    import torch
+    t = torch.zeros(4)
+    with pytest.raises(TypeError):
+        L._dev(t, torch.float32, "q")

@@ -1,0 +1,200 @@
+"""GPU parity: librawalign (HIP, gfx950) against the CPU oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2310_05037_amd import workloads as W
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2310_05037_amd import lib
+    assert torch.cuda.is_available()
+    lib.load()
+    return lib
+
+
+def _run(L, b, **kw):
+    plain = kw.pop("plain", False)
+    opts = L.make_opts(**kw) if kw else None
+    db = L.DeviceBatch(b)
+    db.run(opts=opts, plain=plain)
+    return db.results()
+
+
+def test_config0_single_read(L):
+    b = W.config0()
+    s, e = _run(L, b)
+    st = parity.check(b, s, e)
+    print("config0", st)
+    ps, pe = _run(L, b, plain=True)
+    assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
+    # the true candidate (pair 0) ends inside the read's source window
+    assert int(np.argmin(s)) == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_random_shapes_every_column_class(L, seed):
+    """Region lengths around every columns-per-lane boundary (multiples of
+    256), query lengths from 1 to above the 64-lane skew."""
+    rng = np.random.default_rng(100 + seed)
+    ms = []
+    for k in range(1, 17):
+        ms += [256 * k - 1, 256 * k, 256 * k + 1 if k < 16 else 4096]
+    ms += [1, 2, 3, 63, 64, 65, 127, 128, 129]
+    ns = rng.integers(1, 200, size=len(ms))
+    ns[:6] = [1, 2, 63, 64, 65, 130]
+    reads = [rng.standard_normal(int(n)).astype(np.float32) for n in ns]
+    r = rng.standard_normal(int(sum(ms)) + 7).astype(np.float32)
+    pairs, off = [], 3
+    for i, m in enumerate(ms):
+        pairs.append((i, off, int(m), False))
+        off += int(m)
+    b = W._pack("shapes", reads, pairs, r, {})
+    s, e = _run(L, b)
+    st = parity.check(b, s, e)
+    print("shapes", st)
+
+
+def test_degenerate_and_invalid_pairs(L):
+    import torch
+    rng = np.random.default_rng(7)
+    q = rng.standard_normal(50).astype(np.float32)
+    r = rng.standard_normal(80).astype(np.float32)
+    # (q_off, q_len, r_off, r_len) -> expected sentinel or oracle
+    rows = [(0, 0, 0, 10, (0.0, -1)),          # empty query
+            (0, 5, 0, 0, (math.inf, -1)),      # empty region
+            (0, 0, 0, 0, (0.0, -1)),           # both empty
+            (45, 10, 0, 10, "nan"),            # query slice past the end
+            (0, 5, 75, 10, "nan"),             # region slice past the end
+            (-1, 5, 0, 10, "nan"),             # negative offset
+            (0, -3, 0, 10, "nan"),             # negative length
+            (0, 5, 0, 40000, "nan"),           # region above the maximum
+            (0, 50, 0, 80, None),              # a normal pair in between
+            (10, 1, 5, 1, None)]
+    dev = "cuda"
+    q_off = torch.tensor([x[0] for x in rows], dtype=torch.int64, device=dev)
+    q_len = torch.tensor([x[1] for x in rows], dtype=torch.int32, device=dev)
+    r_off = torch.tensor([x[2] for x in rows], dtype=torch.int64, device=dev)
+    r_len = torch.tensor([x[3] for x in rows], dtype=torch.int32, device=dev)
+    qt = torch.from_numpy(q).to(dev)
+    rt = torch.from_numpy(r).to(dev)
+    for plain in (False, True):
+        sc = torch.full((len(rows),), -7.0, device=dev)
+        en = torch.full((len(rows),), -7, dtype=torch.int32, device=dev)
+        if plain:
+            L.rawalign_dtw_batch(qt, q_off, q_len, rt, r_off, r_len, sc, en)
+        else:
+            L.rawalign_dtw_batch_ex(qt, q_off, q_len, rt, r_off, r_len, sc, en)
+        torch.cuda.synchronize()
+        sc, en = sc.cpu().numpy(), en.cpu().numpy()
+        for i, row in enumerate(rows):
+            exp = row[4]
+            if exp == "nan":
+                assert math.isnan(sc[i]) and en[i] == -2, (i, sc[i], en[i])
+            elif exp is None:
+                qq = q[row[0]:row[0] + row[1]]
+                rr = r[row[2]:row[2] + row[3]]
+                from oracle import oracle
+                c32, e32 = oracle.dtw_f32(qq, rr)
+                assert sc[i] == c32 and en[i] == e32
+            else:
+                assert sc[i] == exp[0] and en[i] == exp[1], (i, sc[i], en[i])
+
+
+def test_config1_full(L):
+    b = W.config1()
+    s, e = _run(L, b)
+    st = parity.check(b, s, e)
+    print("config1", st)
+    ps, pe = _run(L, b, plain=True)
+    assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
+
+
+def test_long_regions_cooperative(L):
+    """Regions above one wave's 4096 columns run on cooperating waves; every
+    split and wave count gives bit-identical results."""
+    rng = np.random.default_rng(3)
+    ms = [4097, 5000, 8191, 8192, 8193, 12000, 16384, 16385, 20000, 24576, 30000, 32768]
+    ns = [1, 2, 64, 65, 97, 200, 33, 130, 250, 7, 100, 64]
+    reads = [rng.standard_normal(n).astype(np.float32) for n in ns]
+    r = rng.standard_normal(sum(ms)).astype(np.float32)
+    pairs, off = [], 0
+    for i, m in enumerate(ms):
+        pairs.append((i, off, m, False))
+        off += m
+    b = W._pack("long", reads, pairs, r, {})
+    s, e = _run(L, b)
+    st = parity.check(b, s, e)
+    print("long", st)
+    for kw in ({"coop_waves": 2}, {"coop_waves": 8}, {"short_max": 1024, "coop_waves": 4}, {"plain": True}):
+        s2, e2 = _run(L, b, **kw)
+        assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2), kw
+
+
+def test_config4_long_stress_sampled(L):
+    """Full 1,024 x (10,000 x 20,000) batch on the GPU, 16 pairs against the
+    oracle."""
+    b = W.config4()
+    s, e = _run(L, b)
+    sample = np.arange(0, b.n_pairs, b.n_pairs // 16)[:16]
+    st = parity.check(b, s, e, pairs=sample)
+    print("config4", st)
+    assert np.isfinite(s).all() and (e >= 0).all() and (e < b.r_len).all()
+
+
+def test_config2_persistent_vs_plain_and_sample(L):
+    """Full 100,000-pair uneven batch: persistent and plain bit-identical,
+    and a stratified sample of 200 pairs against the oracle."""
+    b = W.config2()
+    db = L.DeviceBatch(b)
+    db.run()
+    s, e = db.results()
+    db.run(plain=True)
+    ps, pe = db.results()
+    assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
+    sample = parity.stratified_sample(b, 200)
+    st = parity.check(b, s, e, pairs=sample)
+    print("config2", st)
+    assert np.isfinite(s).all() and (e >= 0).all() and (e < b.r_len).all()
+
+
+def test_exact_inputs_match_double(L):
+    """Quarter-integer inputs keep every sum exact in float, so the GPU must
+    equal the double oracle exactly, designed ties included."""
+    rng = np.random.default_rng(9)
+    b = W.random_pairs(rng, 300, (1, 300), (1, 5000), value_fn=lambda g, n: W.dyadic_values(g, n, -2, 2, 0.5))
+    s, e = _run(L, b)
+    s64, e64, _, _ = parity.oracle_batch(b)
+    assert np.array_equal(s.astype(np.float64), s64) and np.array_equal(e, e64)
+
+
+def test_decide_matches_oracle(L):
+    import torch
+    from oracle import oracle
+    b = W.config1(n_pairs=600)
+    s32, _, _ = oracle.dtw_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
+    s32 = s32.copy()
+    s32[5] = np.inf  # a candidate with an empty region
+    dev = "cuda"
+    n_reads = len(b.cand_off)
+    ob = torch.empty(n_reads, dtype=torch.int32, device=dev)
+    os_ = torch.empty(n_reads, dtype=torch.float64, device=dev)
+    om = torch.empty(n_reads, dtype=torch.uint8, device=dev)
+    cnt = b.cand_cnt.copy()
+    cnt[3] = 0  # a read without candidates
+    for bm, th in ((0.4, 20.0), (0.3, 5.0)):
+        L.rawalign_decide(torch.from_numpy(s32).to(dev), torch.from_numpy(b.cand_off).to(dev),
+                          torch.from_numpy(cnt).to(dev), torch.from_numpy(b.n_events).to(dev),
+                          ob, os_, om, b_match=bm, threshold=th)
+        torch.cuda.synchronize()
+        rb, rs, rm = oracle.decide(s32, b.cand_off, cnt, b.n_events, bm, th)
+        assert np.array_equal(ob.cpu().numpy(), rb)
+        assert np.array_equal(os_.cpu().numpy(), rs)
+        assert np.array_equal(om.cpu().numpy(), rm)
