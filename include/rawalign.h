@@ -57,41 +57,45 @@ extern "C" {
 #define RAWALIGN_ENOMEM (-3)      /* internal scratch allocation failed */
 #define RAWALIGN_ENODEV (-4)      /* no usable gfx950 device */
 
-/* Longest region (levels) a pair may have: 8 cooperating waves x 64 lanes x
- * 64 columns per lane. */
-#define RAWALIGN_MAX_REGION 32768
-/* Longest query (events) a pair may have. */
+/* Longest region (levels) a pair may have: 16 stripes of 64 lanes x 64
+ * columns per lane. */
+#define RAWALIGN_MAX_REGION 65536
+/* Longest query (events) a pair may have; a pair whose region is longer
+ * than one stripe (4096 levels) may have at most RAWALIGN_MAX_QUERY_LONG. */
 #define RAWALIGN_MAX_QUERY (1 << 28)
+#define RAWALIGN_MAX_QUERY_LONG 16384
 
 /* Scheduling modes of rawalign_dtw_batch_ex. */
-#define RAWALIGN_MODE_PLAIN 0       /* one workgroup per pair, input order, fixed split */
-#define RAWALIGN_MODE_PERSISTENT 1  /* persistent grid, atomic work queue, longest pairs first */
+#define RAWALIGN_MODE_PLAIN 0       /* one workgroup per pair in arrival order, fixed grids */
+#define RAWALIGN_MODE_PERSISTENT 1  /* device-sized grids, atomic work queues, longest pairs first */
 
-/* Kernels for pairs above the short/long split. */
-#define RAWALIGN_LONG_STRIPED 0     /* waves own column stripes, edges through LDS rings */
+/* Kernels for regions longer than one stripe (4096 levels). */
+#define RAWALIGN_LONG_STRIPED 0     /* one wave sweeps the stripes in turn, edges through device memory */
 #define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup sweeps anti-diagonals, 3 diagonals in LDS */
 
 /* opts.flags */
 #define RAWALIGN_FLAG_TIMING 1      /* record hipEvents around every kernel (rawalign_last_timing) */
 
 typedef struct rawalign_opts {
-    int32_t mode;          /* RAWALIGN_MODE_*; */
-    int32_t long_kernel;   /* RAWALIGN_LONG_*; */
-    int32_t short_max;     /* pairs with r_len <= short_max run on one wave each (<= 4096);
-                              longer pairs run on a cooperating workgroup.  0 = default */
-    int32_t coop_waves;    /* waves per workgroup for long pairs, 2..8; 0 = default */
-    int32_t waves_per_cu;  /* persistent grid size per CU (0 = occupancy limit) */
-    int32_t flags;         /* RAWALIGN_FLAG_* */
+    int32_t mode;               /* RAWALIGN_MODE_* */
+    int32_t long_kernel;        /* RAWALIGN_LONG_* */
+    int32_t lo_waves_per_cu;    /* persistent grid of the <= 2048-level kernel, per CU (0 = occupancy limit) */
+    int32_t hi_waves_per_cu;    /* same, 2049..4096 levels */
+    int32_t long_waves_per_cu;  /* same, > 4096 levels */
+    int32_t streams;            /* 1: the three kernels run one after another on `stream`;
+                                   3: concurrently on internal streams joined back to `stream` */
+    int32_t flags;              /* RAWALIGN_FLAG_* */
 } rawalign_opts;
 
 /* Fill `opts` with the library defaults (persistent mode, striped long
- * kernel, short_max 4096, 4 cooperating waves).  Returns RAWALIGN_OK. */
+ * kernel, occupancy-sized grids, one stream).  Returns RAWALIGN_OK. */
 int rawalign_opts_default(rawalign_opts *opts);
 
 /*
- * Plain batched subsequence DTW (Sec. 2.2): one launch of the short-pair
- * kernel with one wavefront per pair in input order and one launch of the
- * long-pair kernel for pairs with r_len > 4096.  This is the baseline.
+ * Plain batched subsequence DTW (Sec. 2.2): one wavefront per pair, pairs
+ * taken in arrival order with a static assignment (the baseline).  Three
+ * kernels run one after another: regions of at most 2048 levels, of at most
+ * 4096 levels, and longer regions.
  *
  *   q, r          device, float32 read events / reference levels
  *   q_size, r_size  number of elements in q and r (bounds for the slices)
@@ -173,8 +177,8 @@ int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off
                     int32_t *out_best, double *out_score, uint8_t *out_mapped, void *stream);
 
 /*
- * Autotuner: times candidate settings (short/long split, waves per
- * cooperating workgroup, persistent grid size) on the caller's device batch
+ * Autotuner: times candidate settings (persistent grid sizes of the three
+ * kernels, concurrent or sequential kernels) on the caller's device batch
  * (same layout as rawalign_dtw_batch; out_score/out_end are scratch outputs)
  * and keeps the fastest as this device's tuned setting.  If cache_path is not
  * NULL the result is also written there as JSON keyed by device name, gfx
@@ -192,9 +196,10 @@ int rawalign_load_tuning(const char *cache_path, rawalign_opts *out);
 
 /* Per-kernel timing of the last call made with RAWALIGN_FLAG_TIMING. */
 typedef struct rawalign_timing {
-    float plan_ms;    /* ordering / routing kernels */
-    float short_ms;   /* short-pair kernel */
-    float long_ms;    /* long-pair kernel */
+    float plan_ms;    /* routing / ordering kernels */
+    float lo_ms;      /* regions <= 2048 levels */
+    float hi_ms;      /* regions 2049..4096 levels */
+    float long_ms;    /* regions > 4096 levels */
     float total_ms;   /* first to last event of the call */
 } rawalign_timing;
 int rawalign_last_timing(rawalign_timing *out);

@@ -12,13 +12,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librawalign.so")
 
-SOURCES = ["dtw_kernels.hip", "rawalign_abi.cpp"]
+SOURCES = ["dtw_single.hip", "dtw_multi.hip", "dtw_plan.hip", "rawalign_abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # min-plus arithmetic must not be contracted or reassociated
     "-ffp-contract=off", "-fno-fast-math",
-    # packed FP32 instructions stay off (GPU pool notes)
+    # no packed FP32 instructions (v_pk_*_f32); the DP does not use them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]

@@ -1,0 +1,268 @@
+// dtw_device.h -- device code shared by the gfx950 DTW kernels.
+//
+// The recurrence (RawAlign, arXiv 2310.05037, Sec. 2.2) is a min-plus
+// dynamic program: D(i,j) = |q_i - r_j| + min(D(i-1,j-1), D(i-1,j), D(i,j-1)),
+// row -1 all zero (free start in the region), column -1 +inf.  It is not a
+// contraction, so it runs on the plain FP32 vector ALUs: one v_sub_f32, one
+// v_min3_f32 and one v_add_f32 with an |x| source modifier per cell.
+//
+// Lane-striped wavefront layout (one wave64 per pair):
+//   * the region is cut into S column stripes of 64*C columns; in a stripe
+//     lane k owns C consecutive columns and keeps their levels and the
+//     current DP row in VGPRs while the wave sweeps every query row;
+//   * the sweep is skewed: at step t lane k computes row i = t - k;
+//   * the cell left of lane k's first column comes from lane k-1's last
+//     column of the previous step, and the query event from lane k-1 as
+//     well: both move one lane down per step with a DPP wave_shr:1 move,
+//     lane 0 keeping an injected value (bound_ctrl off);
+//   * lane 0's injected left value is +inf in the first stripe (column -1)
+//     and the previous stripe's last column otherwise; lane 63 writes its
+//     last column to a per-wave edge buffer for the next stripe;
+//   * the per-lane DP row is double-buffered (A -> B on even steps, B -> A on
+//     odd ones), so no register moves are needed inside the loop.
+// Fill/drain steps (t < 64 or t > n-1) leave lanes whose row is outside
+// [0, n) unchanged through a select; in between all 64 lanes are busy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace ra {
+
+#define RA_DEV __device__ __forceinline__
+
+constexpr float kInf = __builtin_inff();
+constexpr int kDppWaveShr1 = 0x138;   // DPP control: whole-wave shift right by one lane
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data)
+
+// Lanes 1..63 receive `src` from lane-1; lane 0 keeps `old_v`.
+RA_DEV float dpp_shr1(float old_v, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old_v),
+                                                                 __builtin_bit_cast(int, src),
+                                                                 kDppWaveShr1, 0xF, 0xF, false));
+}
+
+// One DP cell: rounded subtraction, exact |.|, exact min of three, rounded add.
+RA_DEV float cell(float qv, float rv, float diag, float up, float left) {
+    const float d = qv - rv;
+    return fabsf(d) + fminf(fminf(diag, up), left);
+}
+
+// One query row over the lane's C columns.  Ao = previous row of this lane,
+// diag/left = the previous and current row's value in the column left of the
+// lane, An = new row.
+template <int C>
+RA_DEV void row_step(const float (&rv)[C], float qv, float diag, float left, const float (&Ao)[C],
+                     float (&An)[C]) {
+    An[0] = cell(qv, rv[0], diag, Ao[0], left);
+#pragma unroll
+    for (int s = 1; s < C; ++s) An[s] = cell(qv, rv[s], Ao[s - 1], Ao[s], An[s - 1]);
+}
+
+// Fill/drain form: lanes whose row is outside [0, n) copy the previous row
+// instead (a select, not a branch, so the old and new rows never have to be
+// live at the same time).  Once a lane is past its last row both buffers
+// hold that row.
+template <int C>
+RA_DEV void row_step_masked(bool valid, const float (&rv)[C], float qv, float diag, float left,
+                            const float (&Ao)[C], float (&An)[C]) {
+    float prev = cell(qv, rv[0], diag, Ao[0], left);
+    An[0] = valid ? prev : Ao[0];
+#pragma unroll
+    for (int s = 1; s < C; ++s) {
+        prev = cell(qv, rv[s], Ao[s - 1], Ao[s], prev);
+        An[s] = valid ? prev : Ao[s];
+    }
+}
+
+RA_DEV __amdgpu_buffer_rsrc_t make_rsrc(const float *p, int n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, n * 4, kRsrcWord3);
+}
+
+// Element t (clamped to [0, nm1]) of a buffer, read at one uniform address by
+// every lane; only lane 0 keeps it after the DPP shift.
+RA_DEV float uload(__amdgpu_buffer_rsrc_t rs, int t, int nm1) {
+    const int tt = t < nm1 ? t : nm1;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, tt * 4, 0));
+}
+
+RA_DEV float bload(__amdgpu_buffer_rsrc_t rs, int idx) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4, 0, 0));
+}
+
+// Lane id, opaque to the optimiser.  Every column count has its own code
+// path inside a persistent loop over pairs; if the lane-derived values of all
+// paths were hoisted out of that loop they would stay live together and
+// exhaust the register file.
+RA_DEV int opaque_lane() {
+    int lane = __lane_id();
+    asm volatile("" : "+v"(lane));
+    return lane;
+}
+
+// Lexicographic (value, column) minimum: smallest value, then smallest column.
+RA_DEV void take_min(float &best, int &bj, float v, int j) {
+    if (v < best || (v == best && j < bj)) {
+        best = v;
+        bj = j;
+    }
+}
+
+RA_DEV void wave_min(float &best, int &bj) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ov = __shfl_xor(best, off, 64);
+        const int oj = __shfl_xor(bj, off, 64);
+        take_min(best, bj, ov, oj);
+    }
+}
+
+struct PairView {
+    const float *q;
+    int n;
+    const float *r;
+    int m;
+    float *row;   // resident row (streaming) or null
+    bool fresh;   // row -1 is all zero
+};
+
+template <bool EXT>
+RA_DEV PairView pair_view(const PairArrays &a, int p) {
+    PairView pv;
+    pv.q = a.q + a.q_off[p];
+    pv.n = a.q_len[p];
+    pv.r = a.r + a.r_off[p];
+    pv.m = a.r_len[p];
+    pv.row = EXT ? a.rows + a.row_off[p] : nullptr;
+    pv.fresh = EXT ? a.first_chunk[p] != 0 : true;
+    return pv;
+}
+
+// Registers of one lane: levels, the double-buffered DP row.  Columns are
+// tested against lim = m - col0 (one register) rather than by their index,
+// so no per-column index stays live through the sweep.
+template <int C, bool EXT>
+RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C], float (&B)[C]) {
+    const int lim = pv.m - col0;
+    const int last = lim - 1;
+    const __amdgpu_buffer_rsrc_t rrs = make_rsrc(pv.r, pv.m);
+    __amdgpu_buffer_rsrc_t wrs = rrs;
+    if (EXT) wrs = make_rsrc(pv.row, pv.m);
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        const int jc = col0 + (s < last ? s : last);   // clamped into the region
+        const float lv = bload(rrs, jc);
+        rv[s] = s < lim ? lv : 0.0f;   // padding columns: finite, never reported
+        float init = 0.0f;
+        if (EXT && !pv.fresh) {
+            const float iv = bload(wrs, jc);
+            init = s < lim ? iv : 0.0f;
+        }
+        A[s] = init;
+        B[s] = init;
+    }
+}
+
+// After the sweep every lane has had at least one step past its last row,
+// so A holds row n-1 (or row -1 when n == 0).  Reduce it and optionally
+// store it.
+template <int C, bool EXT>
+RA_DEV void finish_lane(const PairView &pv, int col0, const float (&A)[C], float &best, int &bj) {
+    const int lim = pv.m - col0;
+    best = kInf;
+    bj = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+        if (s < lim) {
+            take_min(best, bj, A[s], col0 + s);
+            if (EXT) pv.row[col0 + s] = A[s];
+        }
+    }
+}
+
+// Two consecutive steps (t even: A -> B, t+1: B -> A).  EIN: lane 0's left
+// values e0/e1 come from the edge buffer (else +inf kept in E0/E1).  EOUT:
+// lane 63 writes its last column of the rows it finished to edge[].
+template <int C, bool MASKED, bool EIN, bool EOUT>
+RA_DEV void two_steps(int t, int n, int lane, const float (&rv)[C], float (&A)[C], float (&B)[C],
+                      float &qv, float q0, float q1, float &E0, float &E1, float e0, float e1,
+                      float *edge) {
+    qv = dpp_shr1(q0, qv);
+    E0 = dpp_shr1(EIN ? e0 : E0, A[C - 1]);
+    if (MASKED) row_step_masked<C>((unsigned)(t - lane) < (unsigned)n, rv, qv, E1, E0, A, B);
+    else row_step<C>(rv, qv, E1, E0, A, B);
+    if (EOUT && t >= 63 && t - 63 < n && lane == 63) edge[t - 63] = B[C - 1];
+    qv = dpp_shr1(q1, qv);
+    E1 = dpp_shr1(EIN ? e1 : E1, B[C - 1]);
+    if (MASKED) row_step_masked<C>((unsigned)(t + 1 - lane) < (unsigned)n, rv, qv, E0, E1, B, A);
+    else row_step<C>(rv, qv, E0, E1, B, A);
+    if (EOUT && t >= 62 && t - 62 < n && lane == 63) edge[t - 62] = A[C - 1];
+}
+
+// One column stripe [col_base, col_base + 64*C) of a pair on one wave.
+// Returns this stripe's (min, argmin) of row n-1 over columns < m.
+template <int C, bool EXT, bool EIN, bool EOUT>
+RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float &best, int &bj) {
+    const int lane = opaque_lane();
+    const int col0 = col_base + lane * C;
+    float rv[C], A[C], B[C];
+    load_lane<C, EXT>(pv, col0, rv, A, B);
+    const int n = pv.n;
+    if (n > 0) {
+        // Left boundary of the region: D(i,-1) = +inf for every row.  At row
+        // 0 the corner D(-1,-1) may be 0, but then D(-1,0) = 0 as well, so
+        // +inf gives the same minimum.
+        float E0 = kInf, E1 = kInf, qv = 0.0f;
+        if (EIN) {
+            // Row 0's north-west neighbour left of this stripe: D(-1, col_base-1).
+            float d0 = 0.0f;
+            if (EXT && !pv.fresh) d0 = pv.row[col_base - 1];
+            E1 = d0;
+        }
+        const __amdgpu_buffer_rsrc_t qrs = make_rsrc(pv.q, n);
+        const __amdgpu_buffer_rsrc_t ers = make_rsrc(edge, n);
+        const int nm1 = n - 1;
+        const int T = (n + 65) & ~1;            // >= n + 64 steps, even
+        const int ta = T < 64 ? T : 64;        // end of the masked fill
+        int tb = n & ~1;                        // end of the unmasked middle
+        if (tb < ta) tb = ta;
+        float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
+        float ea = 0.0f, eb = 0.0f;
+        if (EIN) {
+            ea = uload(ers, 0, nm1);
+            eb = uload(ers, 1, nm1);
+        }
+        int t = 0;
+#define RA_STEPS(MASKED)                                                                     \
+    {                                                                                        \
+        const float q0 = qa, q1 = qb, e0 = ea, e1 = eb;                                      \
+        qa = uload(qrs, t + 2, nm1);                                                         \
+        qb = uload(qrs, t + 3, nm1);                                                         \
+        if (EIN) {                                                                           \
+            ea = uload(ers, t + 2, nm1);                                                     \
+            eb = uload(ers, t + 3, nm1);                                                     \
+        }                                                                                    \
+        two_steps<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, q0, q1, E0, E1, e0, e1, edge); \
+    }
+        for (; t < ta; t += 2) RA_STEPS(true)
+        for (; t < tb; t += 2) RA_STEPS(false)
+        for (; t < T; t += 2) RA_STEPS(true)
+#undef RA_STEPS
+    }
+    finish_lane<C, EXT>(pv, col0, A, best, bj);
+    wave_min(best, bj);
+}
+
+// Stripe shape of a region of m levels: S stripes of 64*C columns, C = 4k.
+// Single-stripe pairs use the smallest k with 256k >= m.  Multi-stripe pairs
+// use S = ceil(m / 4096) and the smallest k with S * 256k >= m; then every
+// stripe starts inside the region ((S-1)*64*C < m for S <= 16).
+RA_DEV void stripe_shape(int m, int &S, int &k) {
+    S = (m + kShortMaxRegion - 1) / kShortMaxRegion;
+    if (S < 1) S = 1;
+    k = (m + 256 * S - 1) / (256 * S);
+}
+
+}  // namespace ra

@@ -1,0 +1,171 @@
+// dtw_plan.hip -- device-side planning (routing, longest-first ordering,
+// sentinels for degenerate or invalid pairs) and the mapping decision.
+#include "dtw_device.h"
+
+namespace ra {
+
+struct PlanArgs {
+    PairArrays a;
+    int64_t n_pairs;
+    int buckets;      // 1: single bucket (plain), kBuckets: LPT buckets
+    int extend;
+    PlanScratch s;
+};
+
+// Route of pair p.  Returns -1 when the pair needs no kernel; then
+// (score, end) is its result: a sentinel for invalid slices (NaN, -2) or the
+// value of a degenerate pair (empty query or empty region).
+RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
+    const PairArrays &a = pa.a;
+    const int n = a.q_len[p];
+    const int m = a.r_len[p];
+    const int64_t qo = a.q_off[p];
+    const int64_t ro = a.r_off[p];
+    bool ok = n >= 0 && m >= 0 && qo >= 0 && ro >= 0 && qo + n <= a.q_size && ro + m <= a.r_size &&
+              m <= kMaxRegion && n <= kMaxQuery && (m <= kShortMaxRegion || n <= kEdgeCap);
+    bool fresh = true;
+    if (pa.extend) {
+        const int64_t wo = a.row_off[p];
+        ok = ok && wo >= 0 && wo + m <= a.rows_size;
+        fresh = a.first_chunk[p] != 0;
+    }
+    if (!ok) {
+        score = __builtin_nanf("");
+        end = -2;
+        return -1;
+    }
+    if (n == 0 && fresh) {
+        score = 0.0f;
+        end = -1;
+        return -1;
+    }
+    if (m == 0) {
+        score = n == 0 ? 0.0f : kInf;
+        end = -1;
+        return -1;
+    }
+    int route;
+    if (m <= kSingleLoMaxRegion) route = kRouteSingleLo;
+    else if (m <= kShortMaxRegion) route = kRouteSingleHi;
+    else route = kRouteMulti;
+    bucket = 0;
+    if (pa.buckets > 1) {
+        // Longest-processing-time order: quarter-octave buckets of the swept
+        // cells (n + 64 steps per stripe x the stripe's padded columns),
+        // bucket 0 holding the largest pairs.
+        int S, k;
+        stripe_shape(m, S, k);
+        const float work = (float)(n + 64) * (float)(S * 256 * k) + 1.0f;
+        int b = (int)(4.0f * __log2f(work));
+        b = b < 0 ? 0 : (b >= pa.buckets ? pa.buckets - 1 : b);
+        bucket = pa.buckets - 1 - b;
+    }
+    return route;
+}
+
+__global__ void k_plan_zero(PlanScratch s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNumRoutes * kBuckets) s.hist[i] = 0;
+    if (i < kNumRoutes) {
+        s.counts[i] = 0;
+        s.queue[i] = 0;
+    }
+}
+
+__global__ void k_plan_count(PlanArgs pa) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pa.n_pairs) return;
+    int b = 0, e = 0;
+    float sc = 0.0f;
+    const int route = classify(pa, p, b, sc, e);
+    if (route >= 0) {
+        atomicAdd(&pa.s.hist[route * kBuckets + b], 1);
+    } else {
+        pa.a.out_score[p] = sc;
+        pa.a.out_end[p] = e;
+    }
+}
+
+// Exclusive scan of each route's histogram (bucket 0 first) -> cursors.
+__global__ void k_plan_scan(PlanScratch s) {
+    const int route = threadIdx.x;
+    if (route >= kNumRoutes) return;
+    int run = 0;
+    for (int b = 0; b < kBuckets; ++b) {
+        const int c = s.hist[route * kBuckets + b];
+        s.hist[route * kBuckets + b] = run;
+        run += c;
+    }
+    s.counts[route] = run;
+    s.queue[route] = 0;
+}
+
+__global__ void k_plan_scatter(PlanArgs pa) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pa.n_pairs) return;
+    int b = 0, e = 0;
+    float sc = 0.0f;
+    const int route = classify(pa, p, b, sc, e);
+    if (route < 0) return;
+    const int pos = atomicAdd(&pa.s.hist[route * kBuckets + b], 1);
+    pa.s.list[route * pa.s.capacity + pos] = (int32_t)p;
+}
+
+hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
+                       hipStream_t stream) {
+    PlanArgs pa;
+    pa.a = a;
+    pa.n_pairs = n_pairs;
+    pa.buckets = cfg.persistent ? kBuckets : 1;
+    pa.extend = a.rows != nullptr;
+    pa.s = s;
+    hipLaunchKernelGGL(k_plan_zero, dim3((kNumRoutes * kBuckets + 255) / 256), dim3(256), 0, stream, s);
+    const unsigned g = (unsigned)((n_pairs + 255) / 256);
+    hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(256), 0, stream, pa);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
+    hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(256), 0, stream, pa);
+    return hipGetLastError();
+}
+
+// ---- mapping decision (Sec. 2.3) ----------------------------------------------
+
+__global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const int64_t *__restrict__ cand_off,
+                         const int32_t *__restrict__ cand_cnt, const int32_t *__restrict__ n_events,
+                         int64_t n_reads, double b_match, double threshold, int32_t *out_best,
+                         double *out_score, uint8_t *out_mapped) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_reads) return;
+    const int64_t p0 = cand_off[k];
+    const int cnt = cand_cnt[k];
+    if (cnt < 0 || p0 < 0 || p0 + cnt > n_pairs) {   // candidate range outside the score array
+        out_best[k] = -2;
+        out_score[k] = __builtin_nan("");
+        out_mapped[k] = 0;
+        return;
+    }
+    // Score = B_Match * N_Read - C_DTW; highest wins, smallest index on ties.
+    const double bonus = b_match * (double)n_events[k];
+    int32_t best = -1;
+    double bs = -__builtin_inf();
+    for (int c = 0; c < cnt; ++c) {
+        const double s = bonus - (double)score[p0 + c];
+        if (best < 0 || s > bs) {
+            best = (int32_t)(p0 + c);
+            bs = s;
+        }
+    }
+    out_best[k] = best;
+    out_score[k] = bs;
+    out_mapped[k] = (best >= 0 && bs >= threshold) ? 1 : 0;
+}
+
+hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
+                         const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
+                         int32_t *out_best, double *out_score, uint8_t *out_mapped, hipStream_t stream) {
+    const unsigned g = (unsigned)((n_reads + 255) / 256);
+    hipLaunchKernelGGL(k_decide, dim3(g), dim3(256), 0, stream, score, n_pairs, cand_off, cand_cnt, n_events,
+                       n_reads, b_match, threshold, out_best, out_score, out_mapped);
+    return hipGetLastError();
+}
+
+}  // namespace ra

@@ -1,0 +1,82 @@
+// dtw_single.hip -- regions of at most 4096 levels: one wave sweeps the
+// whole region as a single stripe (see dtw_device.h for the layout).
+#include "dtw_device.h"
+
+namespace ra {
+
+// C = 4k columns per lane for k in [KLO, KHI]; at most 32 columns fit 128
+// VGPRs (4 waves per SIMD), up to 64 columns fit 256 (2 waves per SIMD).
+template <bool EXT, int KLO, int KHI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KHI <= 8 ? 4 : 2, KHI <= 8 ? 4 : 2)))
+void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+              int32_t *queue) {
+    const int n_items = *count;
+    int item = blockIdx.x;
+    if (queue) {
+        int it = 0;
+        if (__lane_id() == 0) it = atomicAdd(queue, 1);
+        item = __builtin_amdgcn_readfirstlane(it);
+    }
+    while (item < n_items) {
+        const int p = list[item];
+        const PairView pv = pair_view<EXT>(a, p);
+        const int k = (pv.m + 255) >> 8;
+        float best = __builtin_nanf("");
+        int bj = -2;
+#define RA_CASE(K) \
+    if (K >= KLO && K <= KHI && k == K) sweep<4 * K, EXT, false, false>(pv, 0, nullptr, best, bj);
+        RA_CASE(1) RA_CASE(2) RA_CASE(3) RA_CASE(4) RA_CASE(5) RA_CASE(6) RA_CASE(7) RA_CASE(8)
+        RA_CASE(9) RA_CASE(10) RA_CASE(11) RA_CASE(12) RA_CASE(13) RA_CASE(14) RA_CASE(15) RA_CASE(16)
+#undef RA_CASE
+        if (__lane_id() == 0) {
+            a.out_score[p] = best;
+            a.out_end[p] = bj;
+        }
+        if (!queue) break;
+        int it = 0;
+        if (__lane_id() == 0) it = atomicAdd(queue, 1);
+        item = __builtin_amdgcn_readfirstlane(it);
+    }
+}
+
+template <int KLO, int KHI>
+static hipError_t launch_single(int route, int pgrid, const PairArrays &a, int64_t n_pairs,
+                                const LaunchCfg &cfg, const PlanScratch &s, hipStream_t stream) {
+    const int32_t *list = s.list + route * s.capacity;
+    const int32_t *count = s.counts + route;
+    int32_t *queue = cfg.persistent ? s.queue + route : nullptr;
+    // Plain mode: one workgroup per possible item, in list (arrival) order.
+    const unsigned grid = cfg.persistent ? (unsigned)pgrid : (unsigned)n_pairs;
+    if (a.rows)
+        hipLaunchKernelGGL((k_single<true, KLO, KHI>), dim3(grid), dim3(64), 0, stream, a, list, count, queue);
+    else
+        hipLaunchKernelGGL((k_single<false, KLO, KHI>), dim3(grid), dim3(64), 0, stream, a, list, count, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_single_lo(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
+                            hipStream_t stream) {
+    return launch_single<1, 8>(kRouteSingleLo, cfg.lo_grid, a, n_pairs, cfg, s, stream);
+}
+
+hipError_t launch_single_hi(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
+                            hipStream_t stream) {
+    return launch_single<9, 16>(kRouteSingleHi, cfg.hi_grid, a, n_pairs, cfg, s, stream);
+}
+
+template <bool EXT, int KLO, int KHI>
+static int blocks_per_cu() {
+    int nb = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_single<EXT, KLO, KHI>, 64, 0);
+    return nb > 0 ? nb : 1;
+}
+
+int single_lo_blocks_per_cu(bool extend) {
+    return extend ? blocks_per_cu<true, 1, 8>() : blocks_per_cu<false, 1, 8>();
+}
+
+int single_hi_blocks_per_cu(bool extend) {
+    return extend ? blocks_per_cu<true, 9, 16>() : blocks_per_cu<false, 9, 16>();
+}
+
+}  // namespace ra

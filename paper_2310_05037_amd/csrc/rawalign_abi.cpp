@@ -2,7 +2,6 @@
 // argument checks, per-stream scratch, launch order, tuning cache, timing.
 #include <hip/hip_runtime.h>
 
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -17,7 +16,7 @@
 #include "internal.h"
 #include "rawalign.h"
 
-#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.1.0"
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.2.0"
 
 namespace {
 
@@ -43,16 +42,23 @@ std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<int, rawalign_opts> g_tuned;   // device -> tuned settings
 
+// Per (device, user stream) state: planning scratch, edge slots of the
+// multi-stripe kernel, internal streams for concurrent kernels, events.
 struct StreamScratch {
     int32_t *words = nullptr;   // hist | counts | queue
     int32_t *list = nullptr;
     int64_t capacity = 0;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float *edge = nullptr;
+    int64_t edge_slots = 0;
+    hipStream_t sub[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {};      // timing: plan start/end, then start/end of lo, hi, long
 };
 std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
 
 struct TimingRecord {
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {};
     bool valid = false;
 };
 TimingRecord g_last_timing;
@@ -74,20 +80,27 @@ int device_info(int &dev, DeviceInfo &info) {
         it = g_dev.emplace(dev, d).first;
     }
     info = it->second;
-    if (!info.ok) return fail(RAWALIGN_ENODEV, "librawalign is built for gfx950; device " + std::to_string(dev) +
-                                                   " is " + info.arch);
+    if (!info.ok)
+        return fail(RAWALIGN_ENODEV, "librawalign is built for gfx950; device " + std::to_string(dev) + " is " +
+                                         info.arch);
     return RAWALIGN_OK;
 }
 
-int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, bool timing, StreamScratch *&out) {
+int alloc_fail(hipError_t e) {
+    return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+}
+
+int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots, bool timing, bool streams,
+                StreamScratch *&out) {
     std::lock_guard<std::mutex> lk(g_mu);
     StreamScratch &s = g_scratch[{dev, stream}];
+    hipError_t e;
     if (!s.words) {
         const size_t words = (size_t)ra::kNumRoutes * ra::kBuckets + 2 * ra::kNumRoutes;
-        hipError_t e = hipMalloc((void **)&s.words, words * sizeof(int32_t));
+        e = hipMalloc((void **)&s.words, words * sizeof(int32_t));
         if (e != hipSuccess) {
             s.words = nullptr;
-            return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+            return alloc_fail(e);
         }
     }
     if (s.capacity < n_pairs) {
@@ -96,16 +109,37 @@ int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, bool timing, Strea
         if (s.list) (void)hipFree(s.list);
         s.list = nullptr;
         s.capacity = 0;
-        hipError_t e = hipMalloc((void **)&s.list, (size_t)cap * ra::kNumRoutes * sizeof(int32_t));
+        e = hipMalloc((void **)&s.list, (size_t)cap * ra::kNumRoutes * sizeof(int32_t));
         if (e != hipSuccess) {
             s.list = nullptr;
-            return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
+            return alloc_fail(e);
         }
         s.capacity = cap;
     }
+    if (s.edge_slots < edge_slots) {
+        if (s.edge) (void)hipFree(s.edge);
+        s.edge = nullptr;
+        s.edge_slots = 0;
+        e = hipMalloc((void **)&s.edge, (size_t)edge_slots * ra::kEdgeCap * sizeof(float));
+        if (e != hipSuccess) {
+            s.edge = nullptr;
+            return alloc_fail(e);
+        }
+        s.edge_slots = edge_slots;
+    }
+    if (streams && !s.sub[0]) {
+        for (int i = 0; i < 3; ++i) {
+            e = hipStreamCreateWithFlags(&s.sub[i], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+            e = hipEventCreateWithFlags(&s.join[i], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+        e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
     if (timing && !s.ev[0]) {
         for (auto &ev : s.ev) {
-            hipError_t e = hipEventCreate(&ev);
+            e = hipEventCreate(&ev);
             if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         }
     }
@@ -120,6 +154,7 @@ ra::PlanScratch plan_view(StreamScratch &s) {
     p.queue = p.counts + ra::kNumRoutes;
     p.list = s.list;
     p.capacity = s.capacity;
+    p.edge = s.edge;
     return p;
 }
 
@@ -130,21 +165,21 @@ int check_opts(const rawalign_opts &o) {
         return fail(RAWALIGN_EINVAL, "opts.long_kernel RAWALIGN_LONG_ANTIDIAG is not available in this build");
     if (o.long_kernel != RAWALIGN_LONG_STRIPED)
         return fail(RAWALIGN_EINVAL, "opts.long_kernel must be RAWALIGN_LONG_STRIPED or RAWALIGN_LONG_ANTIDIAG");
-    if (o.short_max < 0 || o.short_max > ra::kShortMaxRegion)
-        return fail(RAWALIGN_EINVAL, "opts.short_max must be in [0, 4096]");
-    if (o.coop_waves != 0 && (o.coop_waves < 2 || o.coop_waves > ra::kMaxCoopWaves))
-        return fail(RAWALIGN_EINVAL, "opts.coop_waves must be 0 or in [2, 8]");
-    if (o.waves_per_cu < 0 || o.waves_per_cu > 64)
-        return fail(RAWALIGN_EINVAL, "opts.waves_per_cu must be in [0, 64]");
+    const int32_t w[3] = {o.lo_waves_per_cu, o.hi_waves_per_cu, o.long_waves_per_cu};
+    for (int32_t v : w)
+        if (v < 0 || v > 32) return fail(RAWALIGN_EINVAL, "opts.*_waves_per_cu must be in [0, 32]");
+    if (o.streams != 1 && o.streams != 3) return fail(RAWALIGN_EINVAL, "opts.streams must be 1 or 3");
+    if (o.flags & ~RAWALIGN_FLAG_TIMING) return fail(RAWALIGN_EINVAL, "opts.flags has unknown bits");
     return RAWALIGN_OK;
 }
 
 void defaults(rawalign_opts &o) {
     o.mode = RAWALIGN_MODE_PERSISTENT;
     o.long_kernel = RAWALIGN_LONG_STRIPED;
-    o.short_max = ra::kShortMaxRegion;
-    o.coop_waves = 4;
-    o.waves_per_cu = 0;
+    o.lo_waves_per_cu = 0;
+    o.hi_waves_per_cu = 0;
+    o.long_waves_per_cu = 0;
+    o.streams = 1;
     o.flags = 0;
 }
 
@@ -182,6 +217,8 @@ int check_call(const Call &c) {
     return RAWALIGN_OK;
 }
 
+int grid_of(int cus, int per_cu_opt, int occupancy) { return cus * (per_cu_opt ? per_cu_opt : occupancy); }
+
 int run(const Call &c, const rawalign_opts &o) {
     int rc = check_call(c);
     if (rc) return rc;
@@ -192,9 +229,18 @@ int run(const Call &c, const rawalign_opts &o) {
     DeviceInfo info;
     rc = device_info(dev, info);
     if (rc) return rc;
+
+    const bool ext = c.rows != nullptr;
+    ra::LaunchCfg cfg;
+    cfg.persistent = o.mode == RAWALIGN_MODE_PERSISTENT;
+    cfg.lo_grid = grid_of(info.cus, o.lo_waves_per_cu, ra::single_lo_blocks_per_cu(ext));
+    cfg.hi_grid = grid_of(info.cus, o.hi_waves_per_cu, ra::single_hi_blocks_per_cu(ext));
+    cfg.multi_grid = grid_of(info.cus, o.long_waves_per_cu, ra::multi_blocks_per_cu(ext));
+
     const bool timing = (o.flags & RAWALIGN_FLAG_TIMING) != 0;
+    const bool concurrent = o.streams == 3;
     StreamScratch *s = nullptr;
-    rc = get_scratch(dev, c.stream, c.n_pairs, timing, s);
+    rc = get_scratch(dev, c.stream, c.n_pairs, cfg.multi_grid, timing, concurrent, s);
     if (rc) return rc;
 
     ra::PairArrays a;
@@ -212,41 +258,44 @@ int run(const Call &c, const rawalign_opts &o) {
     a.rows_size = c.rows_size;
     a.row_off = c.row_off;
     a.first_chunk = c.first_chunk;
-
-    ra::LaunchCfg cfg;
-    cfg.short_max = o.short_max;
-    cfg.coop_waves = o.coop_waves ? o.coop_waves : 4;
-    cfg.persistent = o.mode == RAWALIGN_MODE_PERSISTENT;
-    cfg.antidiag = o.long_kernel == RAWALIGN_LONG_ANTIDIAG;
-    const bool ext = c.rows != nullptr;
-    cfg.short_lo_grid = info.cus * (o.waves_per_cu ? o.waves_per_cu : ra::short_blocks_per_cu(ext, false));
-    cfg.short_hi_grid = info.cus * (o.waves_per_cu ? o.waves_per_cu : ra::short_blocks_per_cu(ext, true));
-    cfg.long_grid = info.cus * ra::long_blocks_per_cu(cfg.coop_waves, ext, cfg.antidiag);
-    cfg.huge_grid = info.cus * ra::long_blocks_per_cu(ra::kMaxCoopWaves, ext, cfg.antidiag);
-
     const ra::PlanScratch ps = plan_view(*s);
+
     hipError_t e;
-    if (timing) {
-        e = hipEventRecord(s->ev[0], c.stream);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    }
+    if (timing && (e = hipEventRecord(s->ev[0], c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "plan kernels");
     if (timing) (void)hipEventRecord(s->ev[1], c.stream);
-    // Longest pairs first: they bound the makespan.
-    e = ra::launch_huge(a, c.n_pairs, cfg, ps, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "long-pair kernel (8 waves)");
-    e = ra::launch_long(a, c.n_pairs, cfg, ps, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "long-pair kernel");
-    if (timing) (void)hipEventRecord(s->ev[2], c.stream);
-    e = ra::launch_short_hi(a, c.n_pairs, cfg, ps, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "short-pair kernel (33-64 columns per lane)");
-    e = ra::launch_short_lo(a, c.n_pairs, cfg, ps, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "short-pair kernel (4-32 columns per lane)");
+    hipStream_t st[3] = {c.stream, c.stream, c.stream};
+    if (concurrent) {
+        if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        for (int i = 0; i < 3; ++i) {
+            st[i] = s->sub[i];
+            if ((e = hipStreamWaitEvent(st[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        }
+    }
+    // Longest regions first: they bound the makespan.
+    typedef hipError_t (*Launch)(const ra::PairArrays &, int64_t, const ra::LaunchCfg &, const ra::PlanScratch &,
+                                 hipStream_t);
+    const Launch launches[3] = {ra::launch_multi, ra::launch_single_hi, ra::launch_single_lo};
+    const char *names[3] = {"multi-stripe kernel", "single-stripe kernel (36-64 columns per lane)",
+                            "single-stripe kernel (4-32 columns per lane)"};
+    const int ev_slot[3] = {6, 4, 2};   // long, hi, lo
+    for (int i = 0; i < 3; ++i) {
+        if (timing) (void)hipEventRecord(s->ev[ev_slot[i]], st[i]);
+        e = launches[i](a, c.n_pairs, cfg, ps, st[i]);
+        if (e != hipSuccess) return hip_fail(e, names[i]);
+        if (timing) (void)hipEventRecord(s->ev[ev_slot[i] + 1], st[i]);
+    }
+    if (concurrent) {
+        for (int i = 0; i < 3; ++i) {
+            if ((e = hipEventRecord(s->join[i], st[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+            if ((e = hipStreamWaitEvent(c.stream, s->join[i], 0)) != hipSuccess)
+                return hip_fail(e, "hipStreamWaitEvent");
+        }
+    }
     if (timing) {
-        (void)hipEventRecord(s->ev[3], c.stream);
         std::lock_guard<std::mutex> lk(g_mu);
-        for (int i = 0; i < 4; ++i) g_last_timing.ev[i] = s->ev[i];
+        for (int i = 0; i < 8; ++i) g_last_timing.ev[i] = s->ev[i];
         g_last_timing.valid = true;
     }
     return RAWALIGN_OK;
@@ -292,6 +341,15 @@ bool json_get(const std::string &doc, const std::string &key, std::string &val) 
     size_t e = doc.find_first_of(",}\n", k);
     val = doc.substr(k, e == std::string::npos ? std::string::npos : e - k);
     return true;
+}
+
+const char *kOptNames[] = {"mode", "long_kernel", "lo_waves_per_cu", "hi_waves_per_cu", "long_waves_per_cu",
+                           "streams"};
+
+int32_t *opt_field(rawalign_opts &o, int i) {
+    int32_t *f[] = {&o.mode, &o.long_kernel, &o.lo_waves_per_cu, &o.hi_waves_per_cu, &o.long_waves_per_cu,
+                    &o.streams};
+    return f[i];
 }
 
 }  // namespace
@@ -363,17 +421,25 @@ int rawalign_last_timing(rawalign_timing *out) {
         t = g_last_timing;
     }
     if (!t.valid) return fail(RAWALIGN_EINVAL, "no call with RAWALIGN_FLAG_TIMING yet");
-    hipError_t e = hipEventSynchronize(t.ev[3]);
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    float ms[3];
-    for (int i = 0; i < 3; ++i) {
-        e = hipEventElapsedTime(&ms[i], t.ev[i], t.ev[i + 1]);
+    for (int i = 0; i < 8; ++i) {
+        hipError_t e = hipEventSynchronize(t.ev[i]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    float ms[4];
+    for (int i = 0; i < 4; ++i) {
+        hipError_t e = hipEventElapsedTime(&ms[i], t.ev[2 * i], t.ev[2 * i + 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     }
     out->plan_ms = ms[0];
-    out->long_ms = ms[1];
-    out->short_ms = ms[2];
-    out->total_ms = ms[0] + ms[1] + ms[2];
+    out->lo_ms = ms[1];
+    out->hi_ms = ms[2];
+    out->long_ms = ms[3];
+    float first_to_last = 0.0f;
+    for (int i = 1; i < 8; ++i) {
+        float d = 0.0f;
+        if (hipEventElapsedTime(&d, t.ev[0], t.ev[i]) == hipSuccess && d > first_to_last) first_to_last = d;
+    }
+    out->total_ms = first_to_last;
     return RAWALIGN_OK;
 }
 
@@ -391,19 +457,34 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
     rc = check_call(c);
     if (rc) return rc;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return fail(RAWALIGN_EHIP, "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return fail(RAWALIGN_EHIP, "hipEventCreate");
+    }
+    // Candidates: concurrent or sequential kernels, and persistent grids at
+    // or below the occupancy limit of each kernel.
     std::vector<rawalign_opts> cands;
-    const int splits[] = {2048, 3072, 4096};
-    const int coop[] = {2, 4, 8};
-    for (int sm : splits)
-        for (int cw : coop) {
-            rawalign_opts o;
-            defaults(o);
-            o.short_max = sm;
-            o.coop_waves = cw;
-            cands.push_back(o);
-        }
+    const int lo_occ = ra::single_lo_blocks_per_cu(false);
+    const int hi_occ = ra::single_hi_blocks_per_cu(false);
+    const int mu_occ = ra::multi_blocks_per_cu(false);
+    for (int streams : {1, 3})
+        for (int lo : {lo_occ, lo_occ > 4 ? lo_occ - 4 : lo_occ})
+            for (int hi : {hi_occ, hi_occ > 4 ? hi_occ - 4 : hi_occ})
+                for (int mu : {mu_occ, mu_occ > 4 ? mu_occ - 4 : mu_occ}) {
+                    rawalign_opts o;
+                    defaults(o);
+                    o.streams = streams;
+                    o.lo_waves_per_cu = lo;
+                    o.hi_waves_per_cu = hi;
+                    o.long_waves_per_cu = mu;
+                    bool dup = false;
+                    for (const rawalign_opts &x : cands)
+                        dup = dup || (x.streams == o.streams && x.lo_waves_per_cu == o.lo_waves_per_cu &&
+                                      x.hi_waves_per_cu == o.hi_waves_per_cu &&
+                                      x.long_waves_per_cu == o.long_waves_per_cu);
+                    if (!dup) cands.push_back(o);
+                }
     float best_ms = 1e30f;
     rawalign_opts best;
     defaults(best);
@@ -438,10 +519,9 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
         std::ofstream f(cache_path);
         if (!f) return fail(RAWALIGN_EINVAL, std::string("cannot write ") + cache_path);
         f << "{\"device\": \"" << json_escape(info.name) << "\", \"arch\": \"" << json_escape(info.arch)
-          << "\", \"version\": \"" << RAWALIGN_VERSION_STRING << "\", \"mode\": " << best.mode
-          << ", \"long_kernel\": " << best.long_kernel << ", \"short_max\": " << best.short_max
-          << ", \"coop_waves\": " << best.coop_waves << ", \"waves_per_cu\": " << best.waves_per_cu
-          << ", \"ms\": " << best_ms << "}\n";
+          << "\", \"version\": \"" << RAWALIGN_VERSION_STRING << "\"";
+        for (int i = 0; i < 6; ++i) f << ", \"" << kOptNames[i] << "\": " << *opt_field(best, i);
+        f << ", \"ms\": " << best_ms << "}\n";
     }
     return RAWALIGN_OK;
 }
@@ -464,11 +544,9 @@ int rawalign_load_tuning(const char *cache_path, rawalign_opts *out) {
         return fail(RAWALIGN_EINVAL, "tuning cache is for another library version");
     rawalign_opts o;
     defaults(o);
-    int32_t *fields[] = {&o.mode, &o.long_kernel, &o.short_max, &o.coop_waves, &o.waves_per_cu};
-    const char *names[] = {"mode", "long_kernel", "short_max", "coop_waves", "waves_per_cu"};
-    for (int i = 0; i < 5; ++i) {
-        if (!json_get(doc, names[i], v)) return fail(RAWALIGN_EINVAL, std::string("tuning cache lacks ") + names[i]);
-        *fields[i] = (int32_t)std::strtol(v.c_str(), nullptr, 10);
+    for (int i = 0; i < 6; ++i) {
+        if (!json_get(doc, kOptNames[i], v)) return fail(RAWALIGN_EINVAL, std::string("tuning cache lacks ") + kOptNames[i]);
+        *opt_field(o, i) = (int32_t)std::strtol(v.c_str(), nullptr, 10);
     }
     rc = check_opts(o);
     if (rc) return rc;

@@ -21,7 +21,8 @@ RAWALIGN_EINVAL = -1
 RAWALIGN_EHIP = -2
 RAWALIGN_ENOMEM = -3
 RAWALIGN_ENODEV = -4
-RAWALIGN_MAX_REGION = 32768
+RAWALIGN_MAX_REGION = 65536
+RAWALIGN_MAX_QUERY_LONG = 16384
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 LONG_STRIPED = 0
@@ -43,16 +44,20 @@ class RawAlignError(RuntimeError):
 
 
 class Opts(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int32), ("long_kernel", ctypes.c_int32), ("short_max", ctypes.c_int32),
-                ("coop_waves", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("flags", ctypes.c_int32)]
+    _fields_ = [("mode", ctypes.c_int32), ("long_kernel", ctypes.c_int32), ("lo_waves_per_cu", ctypes.c_int32),
+                ("hi_waves_per_cu", ctypes.c_int32), ("long_waves_per_cu", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("plan_ms", ctypes.c_float), ("short_ms", ctypes.c_float), ("long_ms", ctypes.c_float),
-                ("total_ms", ctypes.c_float)]
+    _fields_ = [("plan_ms", ctypes.c_float), ("lo_ms", ctypes.c_float), ("hi_ms", ctypes.c_float),
+                ("long_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {k: float(getattr(self, k)) for k, _ in self._fields_}
 
 
 _lib = None

@@ -36,7 +36,7 @@ def test_header_declarations_are_exported(L):
 def test_version_and_defaults(L):
     assert L.rawalign_version().startswith("rawalign-mi355x")
     o = L.opts_default()
-    assert o.mode == L.MODE_PERSISTENT and o.short_max == 4096 and o.coop_waves == 4
+    assert o.mode == L.MODE_PERSISTENT and o.streams == 1 and o.lo_waves_per_cu == 0
 
 
 def test_argument_errors_without_device(L):
@@ -58,9 +58,13 @@ def test_argument_errors_without_device(L):
     rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
     assert rc == L.RAWALIGN_EINVAL and b"mode" in so.rawalign_last_error()
     o = L.opts_default()
-    o.coop_waves = 16
+    o.streams = 2
     rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
-    assert rc == L.RAWALIGN_EINVAL and b"coop_waves" in so.rawalign_last_error()
+    assert rc == L.RAWALIGN_EINVAL and b"streams" in so.rawalign_last_error()
+    o = L.opts_default()
+    o.long_waves_per_cu = 99
+    rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"waves_per_cu" in so.rawalign_last_error()
     # extend without a row arena
     rc = so.rawalign_dtw_extend(fake, 10, fake, fake, fake, 10, fake, fake, None, 0, fake, fake, 2, fake, fake,
                                 None, None)

@@ -20,9 +20,15 @@ def L():
     return lib
 
 
+def _say(msg):
+    print(msg, flush=True)
+
+
 def _run(L, b, **kw):
     plain = kw.pop("plain", False)
     opts = L.make_opts(**kw) if kw else None
+    _say(f"  gpu: {b.name} pairs={b.n_pairs} max_n={int(b.q_len.max()) if b.n_pairs else 0} "
+         f"max_m={int(b.r_len.max()) if b.n_pairs else 0} plain={plain} opts={kw}")
     db = L.DeviceBatch(b)
     db.run(opts=opts, plain=plain)
     return db.results()
@@ -75,7 +81,7 @@ def test_degenerate_and_invalid_pairs(L):
             (0, 5, 75, 10, "nan"),             # region slice past the end
             (-1, 5, 0, 10, "nan"),             # negative offset
             (0, -3, 0, 10, "nan"),             # negative length
-            (0, 5, 0, 40000, "nan"),           # region above the maximum
+            (0, 5, 0, 70000, "nan"),           # region above the maximum
             (0, 50, 0, 80, None),              # a normal pair in between
             (10, 1, 5, 1, None)]
     dev = "cuda"
@@ -117,12 +123,12 @@ def test_config1_full(L):
     assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
 
 
-def test_long_regions_cooperative(L):
-    """Regions above one wave's 4096 columns run on cooperating waves; every
-    split and wave count gives bit-identical results."""
+def test_long_regions_multi_stripe(L):
+    """Regions above one stripe's 4096 columns are swept stripe by stripe by
+    one wave; every launch setting gives bit-identical results."""
     rng = np.random.default_rng(3)
-    ms = [4097, 5000, 8191, 8192, 8193, 12000, 16384, 16385, 20000, 24576, 30000, 32768]
-    ns = [1, 2, 64, 65, 97, 200, 33, 130, 250, 7, 100, 64]
+    ms = [4097, 5000, 8191, 8192, 8193, 12000, 16384, 16385, 20000, 24576, 30000, 32768, 40000, 65536]
+    ns = [1, 2, 64, 65, 97, 200, 33, 130, 250, 7, 100, 64, 16384, 70]
     reads = [rng.standard_normal(n).astype(np.float32) for n in ns]
     r = rng.standard_normal(sum(ms)).astype(np.float32)
     pairs, off = [], 0
@@ -133,9 +139,22 @@ def test_long_regions_cooperative(L):
     s, e = _run(L, b)
     st = parity.check(b, s, e)
     print("long", st)
-    for kw in ({"coop_waves": 2}, {"coop_waves": 8}, {"short_max": 1024, "coop_waves": 4}, {"plain": True}):
+    for kw in ({"streams": 3}, {"long_waves_per_cu": 2}, {"plain": True}):
         s2, e2 = _run(L, b, **kw)
         assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2), kw
+
+
+def test_long_query_limit(L):
+    """A multi-stripe pair above the long-query limit gets the sentinel; a
+    single-stripe pair with the same query does not."""
+    rng = np.random.default_rng(4)
+    n = L.RAWALIGN_MAX_QUERY_LONG + 1
+    reads = [rng.standard_normal(n).astype(np.float32)]
+    r = rng.standard_normal(5000).astype(np.float32)
+    b = W._pack("limit", reads, [(0, 0, 4097, False), (0, 0, 300, False)], r, {})
+    s, e = _run(L, b)
+    assert math.isnan(s[0]) and e[0] == -2
+    parity.check(b, s, e, pairs=[1])
 
 
 def test_config4_long_stress_sampled(L):
@@ -154,8 +173,10 @@ def test_config2_persistent_vs_plain_and_sample(L):
     and a stratified sample of 200 pairs against the oracle."""
     b = W.config2()
     db = L.DeviceBatch(b)
+    _say(f"  gpu: {b.name} persistent")
     db.run()
     s, e = db.results()
+    _say(f"  gpu: {b.name} plain")
     db.run(plain=True)
     ps, pe = db.results()
     assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
@@ -190,6 +211,7 @@ def test_decide_matches_oracle(L):
     cnt = b.cand_cnt.copy()
     cnt[3] = 0  # a read without candidates
     for bm, th in ((0.4, 20.0), (0.3, 5.0)):
+        _say(f"  gpu: decide reads={n_reads} b_match={bm} threshold={th}")
         L.rawalign_decide(torch.from_numpy(s32).to(dev), torch.from_numpy(b.cand_off).to(dev),
                           torch.from_numpy(cnt).to(dev), torch.from_numpy(b.n_events).to(dev),
                           ob, os_, om, b_match=bm, threshold=th)
