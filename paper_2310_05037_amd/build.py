@@ -24,31 +24,31 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str = LIB, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     t0 = time.time()
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
+        obj = out + "." + src + ".o"
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     for src, p in procs:
-        out, _ = p.communicate()
-        lines = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
+        log, _ = p.communicate()
+        lines = [ln for ln in log.splitlines() if "packed-fp32-ops" not in ln]
         if p.returncode != 0:
             sys.stderr.write("\n".join(lines) + "\n")
             raise RuntimeError(f"hipcc failed on {src}")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     for o in objs:
         os.remove(o)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s")
-    return LIB
+        print(f"built {out} in {time.time() - t0:.1f}s")
+    return out
 
 
 if __name__ == "__main__":

@@ -33,6 +33,7 @@ namespace ra {
 
 #define RA_DEV __device__ __forceinline__
 
+
 constexpr float kInf = __builtin_inff();
 constexpr int kDppWaveShr1 = 0x138;   // DPP control: whole-wave shift right by one lane
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer descriptor word 3 (32-bit data)
@@ -74,6 +75,31 @@ RA_DEV void row_step_masked(bool valid, const float (&rv)[C], float qv, float di
     for (int s = 1; s < C; ++s) {
         prev = cell(qv, rv[s], Ao[s - 1], Ao[s], prev);
         An[s] = valid ? prev : Ao[s];
+    }
+}
+
+// Two-chain form (lane skew 2): the first half of the lane's columns
+// [0, H) computes row i while the second half [H, C) computes row i-1, so
+// every step carries two independent min-plus chains.  Ao holds [row i-1 |
+// row i-2] and An receives [row i | row i-1]; An[H-1] still holds row i-2
+// of the first half on entry, which is the second half's north-west
+// neighbour, so it is read before the first chain overwrites it.  v1/v2:
+// the rows of the two halves lie in [0, n) (only read when MASKED).
+template <int C, bool MASKED>
+RA_DEV void row_step2(bool v1, bool v2, const float (&rv)[C], float q1, float q2, float diag, float left,
+                      const float (&Ao)[C], float (&An)[C]) {
+    constexpr int H = C / 2;
+    const float d2 = An[H - 1];
+    float f = cell(q1, rv[0], diag, Ao[0], left);
+    float g = cell(q2, rv[H], d2, Ao[H], Ao[H - 1]);
+    An[0] = (MASKED && !v1) ? Ao[0] : f;
+    An[H] = (MASKED && !v2) ? Ao[H] : g;
+#pragma unroll
+    for (int s = 1; s < H; ++s) {
+        f = cell(q1, rv[s], Ao[s - 1], Ao[s], f);
+        g = cell(q2, rv[H + s], Ao[H + s - 1], Ao[H + s], g);
+        An[s] = (MASKED && !v1) ? Ao[s] : f;
+        An[H + s] = (MASKED && !v2) ? Ao[H + s] : g;
     }
 }
 
@@ -201,31 +227,57 @@ RA_DEV void two_steps(int t, int n, int lane, const float (&rv)[C], float (&A)[C
     if (EOUT && t >= 62 && t - 62 < n && lane == 63) edge[t - 62] = A[C - 1];
 }
 
+// Two-chain version of two_steps (see row_step2): lane k computes row
+// t - 2k in its first half and row t - 2k - 1 in its second half.  Qe/Qo
+// hold the first half's query event of the even/odd steps; the second
+// half's event is the other register.  Lane 63's second half finishes row
+// t - 127 at step t.
+template <int C, bool MASKED, bool EIN, bool EOUT>
+RA_DEV void two_steps2(int t, int n, int lane, const float (&rv)[C], float (&A)[C], float (&B)[C],
+                       float &Qe, float &Qo, float q0, float q1, float &E0, float &E1, float e0, float e1,
+                       float *edge) {
+    Qe = dpp_shr1(q0, Qe);
+    E0 = dpp_shr1(EIN ? e0 : E0, A[C - 1]);
+    row_step2<C, MASKED>((unsigned)(t - 2 * lane) < (unsigned)n, (unsigned)(t - 2 * lane - 1) < (unsigned)n,
+                         rv, Qe, Qo, E1, E0, A, B);
+    if (EOUT && t >= 127 && t - 127 < n && lane == 63) edge[t - 127] = B[C - 1];
+    Qo = dpp_shr1(q1, Qo);
+    E1 = dpp_shr1(EIN ? e1 : E1, B[C - 1]);
+    row_step2<C, MASKED>((unsigned)(t + 1 - 2 * lane) < (unsigned)n, (unsigned)(t - 2 * lane) < (unsigned)n,
+                         rv, Qo, Qe, E0, E1, B, A);
+    if (EOUT && t >= 126 && t - 126 < n && lane == 63) edge[t - 126] = A[C - 1];
+}
+
 // One column stripe [col_base, col_base + 64*C) of a pair on one wave.
-// Returns this stripe's (min, argmin) of row n-1 over columns < m.
-template <int C, bool EXT, bool EIN, bool EOUT>
-RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float &best, int &bj) {
+// Returns this stripe's (min, argmin) of row n-1 over columns < m.  ILP2:
+// two independent chains per lane and step (lane skew 2, see row_step2),
+// which pays off on long queries; else one chain (lane skew 1).
+//   corner:      D(-1, col_base-1), row -1 left of this stripe (read when EIN);
+//   next_corner: receives D(-1, col_base+64C-1) for the next stripe.  Both
+//                travel in registers because the resident row is updated in
+//                place, stripe by stripe.
+template <int C, bool EXT, bool EIN, bool EOUT, bool ILP2>
+RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, float &next_corner, float &best,
+                  int &bj) {
     const int lane = opaque_lane();
     const int col0 = col_base + lane * C;
     float rv[C], A[C], B[C];
     load_lane<C, EXT>(pv, col0, rv, A, B);
+    next_corner = __shfl(A[C - 1], 63, 64);
     const int n = pv.n;
     if (n > 0) {
         // Left boundary of the region: D(i,-1) = +inf for every row.  At row
         // 0 the corner D(-1,-1) may be 0, but then D(-1,0) = 0 as well, so
         // +inf gives the same minimum.
-        float E0 = kInf, E1 = kInf, qv = 0.0f;
-        if (EIN) {
-            // Row 0's north-west neighbour left of this stripe: D(-1, col_base-1).
-            float d0 = 0.0f;
-            if (EXT && !pv.fresh) d0 = pv.row[col_base - 1];
-            E1 = d0;
-        }
+        float E0 = kInf, E1 = kInf, qv = 0.0f, qo = 0.0f;
+        if (EIN) E1 = corner;   // row 0's north-west neighbour left of this stripe
         const __amdgpu_buffer_rsrc_t qrs = make_rsrc(pv.q, n);
         const __amdgpu_buffer_rsrc_t ers = make_rsrc(edge, n);
         const int nm1 = n - 1;
-        const int T = (n + 65) & ~1;            // >= n + 64 steps, even
-        const int ta = T < 64 ? T : 64;        // end of the masked fill
+        // Every lane gets at least one step past its last row.
+        const int skew = ILP2 ? 128 : 64;    // steps until lane 63 starts its last rows
+        const int T = (n + skew + 1) & ~1;      // >= n + skew steps, even
+        const int ta = T < skew ? T : skew;     // end of the masked fill
         int tb = n & ~1;                        // end of the unmasked middle
         if (tb < ta) tb = ta;
         float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
@@ -244,7 +296,10 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float &best, in
             ea = uload(ers, t + 2, nm1);                                                     \
             eb = uload(ers, t + 3, nm1);                                                     \
         }                                                                                    \
-        two_steps<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, q0, q1, E0, E1, e0, e1, edge); \
+        if (ILP2)                                                                            \
+            two_steps2<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, qo, q0, q1, E0, E1, e0, e1, edge); \
+        else                                                                                 \
+            two_steps<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, q0, q1, E0, E1, e0, e1, edge); \
     }
         for (; t < ta; t += 2) RA_STEPS(true)
         for (; t < tb; t += 2) RA_STEPS(false)

@@ -10,13 +10,15 @@ template <int C, bool EXT>
 RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int &bj) {
     best = kInf;
     bj = 0x7fffffff;
+    float corner = 0.0f;   // D(-1, col_base-1) of the next stripe
     for (int s = 0; s < S; ++s) {
-        float b;
+        float b, nc;
         int j;
         if (s == 0)
-            sweep<C, EXT, false, true>(pv, 0, edge, b, j);
+            sweep<C, EXT, false, true, true>(pv, 0, edge, 0.0f, nc, b, j);
         else
-            sweep<C, EXT, true, true>(pv, s * 64 * C, edge, b, j);
+            sweep<C, EXT, true, true, true>(pv, s * 64 * C, edge, corner, nc, b, j);
+        corner = nc;
         take_min(best, bj, b, j);
         // Lane 63's edge stores must be visible to lane 0 of the next stripe.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -23,8 +23,9 @@ void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__r
         const int k = (pv.m + 255) >> 8;
         float best = __builtin_nanf("");
         int bj = -2;
+        float nc;
 #define RA_CASE(K) \
-    if (K >= KLO && K <= KHI && k == K) sweep<4 * K, EXT, false, false>(pv, 0, nullptr, best, bj);
+    if (K >= KLO && K <= KHI && k == K) sweep<4 * K, EXT, false, false, false>(pv, 0, nullptr, 0.0f, nc, best, bj);
         RA_CASE(1) RA_CASE(2) RA_CASE(3) RA_CASE(4) RA_CASE(5) RA_CASE(6) RA_CASE(7) RA_CASE(8)
         RA_CASE(9) RA_CASE(10) RA_CASE(11) RA_CASE(12) RA_CASE(13) RA_CASE(14) RA_CASE(15) RA_CASE(16)
 #undef RA_CASE

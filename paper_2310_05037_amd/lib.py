@@ -70,6 +70,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so device memory and streams from torch are valid in it.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     pair_args = [vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp]

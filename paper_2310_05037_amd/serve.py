@@ -1,0 +1,443 @@
+"""Read Until serving loop: streamed chunks, resident DTW rows, continuous batching.
+
+RawAlign decides per chunk of sequenced signal whether a read maps (Sec. 1:
+timely decisions; Sec. 3.1.2: one chunk is the data of about one second of
+sequencing; Sec. 2.3: Score = B_Match * N_Read - C_DTW, mapped iff the best
+score reaches Score_Threshold).  This module keeps, for every candidate of
+every admitted read, the last DTW row of the events seen so far in a device
+row arena, so each new chunk extends the alignment instead of redoing it.
+
+Engine (host logic only):
+  * admission: a read is admitted when its first chunk is available and the
+    arena has room for one row per candidate (4 bytes per region level);
+    reads that do not fit wait in arrival order (back-pressure);
+  * continuous batching: every tick takes all chunks available at that
+    moment from all admitted reads, whatever their sizes, as one job table
+    (one job per candidate) and runs the extend and decision kernels once;
+  * a read finishes when it maps or after its last chunk; its rows are
+    freed and waiting reads may be admitted;
+  * per chunk it records the latency from the moment the chunk became
+    available to the moment its decision is on the host.
+Backends: GpuBackend (librawalign, optionally replaying one captured HIP
+graph per tick) and, for tests of the scheduling logic only, a backend
+built on the CPU oracle (tests/).
+"""
+from __future__ import annotations
+
+import bisect
+import collections
+import heapq
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+B_MATCH = 0.4
+SCORE_THRESHOLD = 20.0
+
+
+class ArenaFull(Exception):
+    pass
+
+
+class RowArena:
+    """First-fit allocator of float offsets in a buffer of `size` floats."""
+
+    def __init__(self, size: int):
+        self.size = int(size)
+        self.free = [(0, self.size)]   # sorted (offset, length)
+        self.used = 0
+
+    def alloc(self, n: int) -> int:
+        n = int(n)
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                self.used += n
+                return off
+        raise ArenaFull(n)
+
+    def release(self, off: int, n: int):
+        off, n = int(off), int(n)
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, n))
+        # merge with neighbours
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+        self.used -= n
+
+    def largest(self) -> int:
+        return max((ln for _, ln in self.free), default=0)
+
+
+@dataclass(eq=False)
+class ReadState:
+    rid: int
+    arrival: float
+    events: np.ndarray
+    r_off: np.ndarray
+    r_len: np.ndarray
+    chunk: int
+    n_chunks: int = 0
+    next_chunk: int = 0          # next chunk index to process
+    row_off: np.ndarray | None = None
+    admitted: bool = False
+    done: bool = False
+    status: str = "waiting"      # waiting | active | mapped | unmapped | cancelled | failed
+    results: list = field(default_factory=list)   # per chunk: (best_pair, score, mapped, c_dtw[], end[])
+
+    def chunk_ready_time(self, c: int, period: float) -> float:
+        return self.arrival + c * period
+
+
+@dataclass
+class TickBatch:
+    """Jobs of one tick.  Read t of the tick owns jobs cand_off[t] ..
+    cand_off[t]+cand_cnt[t]-1; its chunk events are chunks[t]."""
+    reads: list
+    chunks: list
+    r_off: np.ndarray
+    r_len: np.ndarray
+    row_off: np.ndarray
+    first: np.ndarray
+    cand_off: np.ndarray
+    cand_cnt: np.ndarray
+    n_events: np.ndarray
+
+    @property
+    def n_jobs(self) -> int:
+        return int(len(self.r_off))
+
+    @property
+    def cells(self) -> int:
+        lens = np.repeat(np.array([len(c) for c in self.chunks], np.int64), self.cand_cnt)
+        return int(np.dot(lens, self.r_len.astype(np.int64)))
+
+
+class Engine:
+    def __init__(self, backend, arena_floats: int, chunk: int = 400, period: float = 1.0,
+                 b_match: float = B_MATCH, threshold: float = SCORE_THRESHOLD, max_jobs: int = 1 << 15,
+                 max_reads: int = 4096, clock=None):
+        self.backend = backend
+        self.arena = RowArena(arena_floats)
+        self.chunk = chunk
+        self.period = period
+        self.b_match = b_match
+        self.threshold = threshold
+        self.max_jobs = max_jobs
+        self.max_reads = max_reads
+        self.clock = clock or time.perf_counter
+        self.reads: list[ReadState] = []     # in submission order
+        self.by_id: dict[int, ReadState] = {}
+        self.future: list[ReadState] = []    # not yet available, sorted by arrival
+        self.next_future = 0
+        self.pending = collections.deque()   # available, waiting for arena room (arrival order)
+        self.heap = []                       # (next chunk ready time, seq, read id) of admitted reads
+        self.seq = 0
+        self.n_done = 0
+        self.latencies = []                  # (read id, chunk, latency seconds)
+        self.ticks = 0
+        self.cells = 0
+        self.jobs = 0
+        self.rejected = 0
+        self.peak_arena = 0
+        self.failed_ticks = 0
+
+    # ---- submission ------------------------------------------------------------
+    def submit(self, rid: int, arrival: float, events: np.ndarray, r_off, r_len):
+        """Register a read whose first chunk is available at `arrival`; chunk
+        c is available at arrival + c * period.  Submit in arrival order."""
+        r_off = np.asarray(r_off, np.int64)
+        r_len = np.asarray(r_len, np.int32)
+        st = ReadState(rid, arrival, np.ascontiguousarray(events, np.float32), r_off, r_len, self.chunk)
+        st.n_chunks = (len(events) + self.chunk - 1) // self.chunk
+        self.reads.append(st)
+        self.by_id[rid] = st
+        if int(r_len.sum()) > self.arena.size or st.n_chunks == 0:
+            st.status = "failed"     # can never fit (or nothing to do): refuse instead of blocking the queue
+            st.done = True
+            self.n_done += 1
+            self.rejected += 1
+        else:
+            if self.future and arrival < self.future[-1].arrival:
+                raise ValueError("submit reads in arrival order")
+            self.future.append(st)
+        return st
+
+    def cancel(self, rid: int):
+        st = self.by_id.get(rid)
+        if st is not None and not st.done:
+            self._finish(st, "cancelled")
+
+    # ---- scheduling ------------------------------------------------------------
+    def _finish(self, st: ReadState, status: str):
+        if st.admitted and st.row_off is not None:
+            for off, ln in zip(st.row_off, st.r_len):
+                self.arena.release(off, ln)
+        st.row_off = None
+        st.done = True
+        st.status = status
+        self.n_done += 1
+        if not st.admitted and st in self.pending:
+            self.pending.remove(st)
+
+    def _push(self, st: ReadState):
+        heapq.heappush(self.heap, (st.chunk_ready_time(st.next_chunk, self.period), self.seq, st.rid))
+        self.seq += 1
+
+    def _admit(self, now: float):
+        while self.next_future < len(self.future) and self.future[self.next_future].arrival <= now:
+            st = self.future[self.next_future]
+            self.next_future += 1
+            if not st.done:
+                self.pending.append(st)
+        # arrival order: nobody overtakes a read that does not fit yet
+        while self.pending:
+            st = self.pending[0]
+            offs = []
+            try:
+                for ln in st.r_len:
+                    offs.append(self.arena.alloc(ln))
+            except ArenaFull:
+                for off, ln in zip(offs, st.r_len):
+                    self.arena.release(off, ln)
+                break
+            self.pending.popleft()
+            st.row_off = np.array(offs, np.int64)
+            st.admitted = True
+            st.status = "active"
+            self._push(st)
+        self.peak_arena = max(self.peak_arena, self.arena.used)
+
+    def _ready(self, now: float):
+        out, jobs = [], 0
+        while self.heap and self.heap[0][0] <= now and len(out) < self.max_reads:
+            _, _, rid = self.heap[0]
+            st = self.by_id[rid]
+            if st.done:
+                heapq.heappop(self.heap)
+                continue
+            if out and jobs + len(st.r_len) > self.max_jobs:
+                break
+            heapq.heappop(self.heap)
+            out.append(st)
+            jobs += len(st.r_len)
+        return out
+
+    def _batch(self, ready) -> TickBatch:
+        chunks, first, cand_cnt, n_ev = [], [], [], []
+        for st in ready:
+            c = st.next_chunk
+            chunks.append(st.events[c * self.chunk:(c + 1) * self.chunk])
+            first.append(np.full(len(st.r_len), 1 if c == 0 else 0, np.uint8))
+            cand_cnt.append(len(st.r_len))
+            n_ev.append(min((c + 1) * self.chunk, len(st.events)))
+        cc = np.array(cand_cnt, np.int32)
+        return TickBatch(list(ready), chunks, np.concatenate([st.r_off for st in ready]),
+                         np.concatenate([st.r_len for st in ready]), np.concatenate([st.row_off for st in ready]),
+                         np.concatenate(first), np.concatenate([[0], np.cumsum(cc)[:-1]]).astype(np.int64), cc,
+                         np.array(n_ev, np.int32))
+
+    def tick(self) -> int:
+        """One scheduling step; returns the number of chunks processed."""
+        now = self.clock()
+        self._admit(now)
+        ready = self._ready(now)
+        if not ready:
+            return 0
+        b = self._batch(ready)
+        try:
+            score, end, best, best_score, mapped = self.backend.run(b, self.b_match, self.threshold)
+        except Exception:
+            # fail only the reads of this tick; the rest continue
+            self.failed_ticks += 1
+            for st in b.reads:
+                self._finish(st, "failed")
+            return 0
+        t_done = self.clock()
+        self.ticks += 1
+        self.jobs += b.n_jobs
+        self.cells += b.cells
+        for t, st in enumerate(b.reads):
+            lo, k = int(b.cand_off[t]), int(b.cand_cnt[t])
+            c = st.next_chunk
+            st.results.append((int(best[t]) - lo if best[t] >= 0 else -1, float(best_score[t]), int(mapped[t]),
+                               score[lo:lo + k].copy(), end[lo:lo + k].copy()))
+            self.latencies.append((st.rid, c, t_done - st.chunk_ready_time(c, self.period)))
+            st.next_chunk += 1
+            if st.done:                      # cancelled while its chunk was in flight
+                continue
+            if mapped[t]:
+                self._finish(st, "mapped")
+            elif st.next_chunk >= st.n_chunks:
+                self._finish(st, "unmapped")
+            else:
+                self._push(st)
+        return len(b.reads)
+
+    def all_done(self) -> bool:
+        return self.n_done == len(self.reads)
+
+    def next_event_time(self) -> float | None:
+        t = []
+        if self.heap:
+            t.append(self.heap[0][0])
+        if self.next_future < len(self.future):
+            t.append(self.future[self.next_future].arrival)
+        return min(t) if t else None
+
+    def run(self, idle_sleep: float = 2e-4, timeout: float | None = None):
+        t0 = self.clock()
+        while not self.all_done():
+            if self.tick() == 0:
+                if timeout is not None and self.clock() - t0 > timeout:
+                    raise TimeoutError("serving loop did not finish")
+                nxt = self.next_event_time()
+                if nxt is None and self.pending:
+                    raise RuntimeError("reads wait for arena room that no running read will free")
+                wait = idle_sleep if nxt is None else min(max(nxt - self.clock(), 0.0), idle_sleep)
+                if wait > 0:
+                    time.sleep(wait)
+
+    def stats(self) -> dict:
+        lat = np.array([x[2] for x in self.latencies]) if self.latencies else np.zeros(1)
+        st = [s.status for s in self.reads]
+        return {"chunks": len(self.latencies), "reads": len(self.reads), "ticks": self.ticks, "jobs": self.jobs,
+                "cells": self.cells, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "p999_ms": float(np.percentile(lat, 99.9) * 1e3),
+                "max_ms": float(lat.max() * 1e3), "mapped": st.count("mapped"), "unmapped": st.count("unmapped"),
+                "failed": st.count("failed"), "cancelled": st.count("cancelled"),
+                "peak_arena_bytes": int(self.peak_arena) * 4, "arena_bytes": self.arena.size * 4}
+
+
+class GpuBackend:
+    """librawalign on one device: rawalign_dtw_extend over the tick's jobs,
+    then rawalign_decide over its reads.  With use_graph, the tick (pinned
+    host-to-device copies, both library calls, device-to-host copies) is
+    captured once into a HIP graph over fixed-capacity tables and replayed;
+    unused job slots carry q_len = -1 (sentinel, no kernel work) and unused
+    read slots no candidates."""
+
+    def __init__(self, r_levels: np.ndarray, arena_floats: int, chunk: int = 400, max_jobs: int = 1 << 15,
+                 max_reads: int = 4096, use_graph: bool = True, opts=None):
+        import torch
+        from . import lib
+        self.torch, self.lib = torch, lib
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.chunk, self.max_jobs, self.max_reads = chunk, max_jobs, max_reads
+        self.r = torch.from_numpy(np.ascontiguousarray(r_levels, np.float32)).to(dev)
+        self.rows = torch.zeros(int(arena_floats), dtype=torch.float32, device=dev)
+        self.opts = opts
+        pin = dict(pin_memory=True)
+        J, R = max_jobs, max_reads
+        self.h = {"q": torch.zeros(R * chunk, dtype=torch.float32, **pin),
+                  "q_off": torch.zeros(J, dtype=torch.int64, **pin), "q_len": torch.zeros(J, dtype=torch.int32, **pin),
+                  "r_off": torch.zeros(J, dtype=torch.int64, **pin), "r_len": torch.zeros(J, dtype=torch.int32, **pin),
+                  "row_off": torch.zeros(J, dtype=torch.int64, **pin), "first": torch.zeros(J, dtype=torch.uint8, **pin),
+                  "cand_off": torch.zeros(R, dtype=torch.int64, **pin), "cand_cnt": torch.zeros(R, dtype=torch.int32, **pin),
+                  "n_events": torch.zeros(R, dtype=torch.int32, **pin)}
+        self.d = {k: torch.empty_like(v, device=dev) for k, v in self.h.items()}
+        self.d_out = {"score": torch.empty(J, dtype=torch.float32, device=dev),
+                      "end": torch.empty(J, dtype=torch.int32, device=dev),
+                      "best": torch.empty(R, dtype=torch.int32, device=dev),
+                      "best_score": torch.empty(R, dtype=torch.float64, device=dev),
+                      "mapped": torch.empty(R, dtype=torch.uint8, device=dev)}
+        self.h_out = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in self.d_out.items()}
+        self.stream = torch.cuda.Stream()
+        self.use_graph = use_graph
+        self.graph = None
+        self.params = None
+
+    def _work(self, b_match, threshold):
+        d, o = self.d, self.d_out
+        for k in self.h:
+            d[k].copy_(self.h[k], non_blocking=True)
+        self.lib.rawalign_dtw_extend(d["q"], d["q_off"], d["q_len"], self.r, d["r_off"], d["r_len"], self.rows,
+                                     d["row_off"], d["first"], o["score"], o["end"], opts=self.opts)
+        self.lib.rawalign_decide(o["score"], d["cand_off"], d["cand_cnt"], d["n_events"], o["best"],
+                                 o["best_score"], o["mapped"], b_match=b_match, threshold=threshold)
+        for k in o:
+            self.h_out[k].copy_(o[k], non_blocking=True)
+
+    def _fill(self, b: TickBatch):
+        h = self.h
+        nj, nr = b.n_jobs, len(b.reads)
+        if nj > self.max_jobs or nr > self.max_reads:
+            raise ValueError("tick larger than the backend tables")
+        q = h["q"].numpy()
+        lens = np.zeros(nr, np.int32)
+        for t, ev in enumerate(b.chunks):
+            q[t * self.chunk:t * self.chunk + len(ev)] = ev
+            lens[t] = len(ev)
+        job_read = np.repeat(np.arange(nr), b.cand_cnt)
+        h["q_off"].numpy()[:nj] = job_read * self.chunk
+        ql = h["q_len"].numpy()
+        ql[:nj] = lens[job_read]
+        ql[nj:] = -1                           # empty slots: sentinel, no kernel work
+        h["r_off"].numpy()[:nj] = b.r_off
+        h["r_len"].numpy()[:nj] = b.r_len
+        h["row_off"].numpy()[:nj] = b.row_off
+        h["first"].numpy()[:nj] = b.first
+        h["cand_off"].numpy()[:nr] = b.cand_off
+        cc = h["cand_cnt"].numpy()
+        cc[:nr] = b.cand_cnt
+        cc[nr:] = 0
+        h["n_events"].numpy()[:nr] = b.n_events
+
+    def _blank(self):
+        self.h["q_len"].fill_(-1)
+        self.h["cand_cnt"].fill_(0)
+
+    def run(self, b: TickBatch, b_match: float, threshold: float):
+        torch = self.torch
+        self._fill(b)
+        with torch.cuda.stream(self.stream):
+            if not self.use_graph:
+                self._work(b_match, threshold)
+            else:
+                if self.graph is None or self.params != (b_match, threshold):
+                    # Warm-up over blank tables (every slot a sentinel, the rows
+                    # untouched) so the library allocates its scratch outside
+                    # the capture; then capture the real tables' tick.
+                    self._blank()
+                    self._work(b_match, threshold)
+                    self.stream.synchronize()
+                    self._fill(b)
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=self.stream):
+                        self._work(b_match, threshold)
+                    self.graph, self.params = g, (b_match, threshold)
+                self.graph.replay()
+        self.stream.synchronize()
+        nj, nr = b.n_jobs, len(b.reads)
+        o = self.h_out
+        return (o["score"].numpy()[:nj].copy(), o["end"].numpy()[:nj].copy(), o["best"].numpy()[:nr].copy(),
+                o["best_score"].numpy()[:nr].copy(), o["mapped"].numpy()[:nr].copy())
+
+
+def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
+          max_jobs: int = 1 << 15, max_reads: int = 4096, timeout: float | None = None, backend=None):
+    """Run a workloads.ServingWorkload through the engine on the GPU.
+    time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
+    period becomes 10 ms)."""
+    arena_floats = arena_bytes // 4
+    if backend is None:
+        backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph)
+    eng = Engine(backend, arena_floats, workload.chunk, workload.period * time_scale, max_jobs=max_jobs,
+                 max_reads=max_reads)
+    t0 = eng.clock()
+    for i, rd in enumerate(workload.reads):
+        eng.submit(i, t0 + rd.arrival * time_scale, rd.events, rd.r_off, rd.r_len)
+    eng.run(timeout=timeout)
+    wall = eng.clock() - t0
+    st = eng.stats()
+    st.update({"wall_s": wall, "gcups": eng.cells / wall / 1e9, "chunks_per_s": st["chunks"] / wall,
+               "time_scale": time_scale, "rate_reads_per_s": workload.rate / time_scale})
+    return eng, st

@@ -1,0 +1,150 @@
+"""GPU parity of the streaming extension (resident rows) and the serving loop."""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2310_05037_amd import workloads as W
+
+from . import parity
+from .serving_oracle import OracleBackend
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2310_05037_amd import lib
+    assert torch.cuda.is_available()
+    lib.load()
+    return lib
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _extend_round(L, q_chunks, r, r_off, r_len, rows, row_off, first):
+    """One rawalign_dtw_extend call; q_chunks[k] is job k's chunk."""
+    import torch
+    lens = np.array([len(c) for c in q_chunks], np.int32)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    q = np.concatenate(q_chunks + [np.zeros(1, np.float32)]).astype(np.float32)
+    dev = "cuda"
+    n = len(q_chunks)
+    sc = torch.empty(n, dtype=torch.float32, device=dev)
+    en = torch.empty(n, dtype=torch.int32, device=dev)
+    L.rawalign_dtw_extend(torch.from_numpy(q).to(dev), torch.from_numpy(offs).to(dev),
+                          torch.from_numpy(lens).to(dev), r, torch.from_numpy(r_off).to(dev),
+                          torch.from_numpy(r_len).to(dev), rows, torch.from_numpy(row_off).to(dev),
+                          torch.from_numpy(first).to(dev), sc, en)
+    torch.cuda.synchronize()
+    return sc.cpu().numpy(), en.cpu().numpy()
+
+
+def test_extend_chunked_equals_whole_prefix(L):
+    """Streaming a query chunk by chunk through the resident rows gives, after
+    every chunk, the float oracle's result on the whole prefix, bit for bit;
+    regions span one and several stripes; chunk sizes vary and include
+    empty chunks."""
+    import torch
+    rng = np.random.default_rng(21)
+    n_jobs = 24
+    ms = rng.integers(1, 9000, n_jobs)
+    ms[:6] = [1, 64, 4096, 4097, 8192, 8999]
+    r_np = rng.standard_normal(int(ms.sum())).astype(np.float32)
+    r_off = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64)
+    r_len = ms.astype(np.int32)
+    queries = [rng.standard_normal(int(rng.integers(1, 900))).astype(np.float32) for _ in range(n_jobs)]
+    row_off = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64) + 5
+    rows = torch.full((int(ms.sum()) + 10,), -1.0, device="cuda")
+    r = torch.from_numpy(r_np).to("cuda")
+    pos = np.zeros(n_jobs, np.int64)
+    rounds = 0
+    while (pos < [len(x) for x in queries]).any() or rounds == 0:
+        sizes = rng.integers(0, 300, n_jobs)
+        sizes[rounds % n_jobs] = 0   # an empty chunk somewhere every round
+        chunks, first = [], np.zeros(n_jobs, np.uint8)
+        for k in range(n_jobs):
+            a, b = int(pos[k]), int(min(pos[k] + sizes[k], len(queries[k])))
+            chunks.append(queries[k][a:b])
+            first[k] = 1 if a == 0 else 0   # no events seen yet: row -1 is zero
+            pos[k] = b
+        _say(f"  gpu: extend round {rounds} jobs={n_jobs}")
+        sc, en = _extend_round(L, chunks, r, r_off, r_len, rows, row_off, first)
+        for k in range(n_jobs):
+            prefix = queries[k][:int(pos[k])]
+            c32, e32 = oracle.dtw_f32(prefix, r_np[r_off[k]:r_off[k] + r_len[k]])
+            assert sc[k].view(np.uint32) == np.float32(c32).view(np.uint32) and en[k] == e32, (rounds, k)
+        rounds += 1
+    # the arena outside the rows is untouched
+    assert rows[:5].eq(-1).all() and rows[-5:].eq(-1).all()
+    for k in range(n_jobs):
+        c64, e64 = oracle.dtw_f64(queries[k], r_np[r_off[k]:r_off[k] + r_len[k]])
+        assert abs(float(sc[k]) - c64) <= parity.REL_TOL * c64 + parity.ABS_TOL
+
+
+def test_extend_alone_equals_mix(L):
+    """A job gives the same bits alone and inside a mix of jobs of other
+    sizes (continuous batching changes nothing but throughput)."""
+    import torch
+    rng = np.random.default_rng(22)
+    n_jobs = 40
+    ms = rng.integers(100, 7000, n_jobs).astype(np.int32)
+    r_np = rng.standard_normal(int(ms.sum())).astype(np.float32)
+    r_off = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64)
+    chunks1 = [rng.standard_normal(int(rng.integers(1, 500))).astype(np.float32) for _ in range(n_jobs)]
+    chunks2 = [rng.standard_normal(int(rng.integers(1, 500))).astype(np.float32) for _ in range(n_jobs)]
+    r = torch.from_numpy(r_np).to("cuda")
+    row_off = r_off.copy()
+    rows_mix = torch.zeros(int(ms.sum()), device="cuda")
+    _say("  gpu: extend mix")
+    _extend_round(L, chunks1, r, r_off, ms, rows_mix, row_off, np.ones(n_jobs, np.uint8))
+    mix = _extend_round(L, chunks2, r, r_off, ms, rows_mix, row_off, np.zeros(n_jobs, np.uint8))
+    for k in range(0, n_jobs, 7):
+        rows1 = torch.zeros(int(ms[k]), device="cuda")
+        _say(f"  gpu: extend alone job {k}")
+        one = np.array([0], np.int64)
+        _extend_round(L, [chunks1[k]], r, r_off[k:k + 1], ms[k:k + 1], rows1, one, np.ones(1, np.uint8))
+        a = _extend_round(L, [chunks2[k]], r, r_off[k:k + 1], ms[k:k + 1], rows1, one, np.zeros(1, np.uint8))
+        assert a[0][0].view(np.uint32) == mix[0][k].view(np.uint32) and a[1][0] == mix[1][k]
+        assert torch.equal(rows1, rows_mix[int(row_off[k]):int(row_off[k]) + int(ms[k])])
+
+
+def _oracle_engine(wl):
+    from paper_2310_05037_amd import serve
+
+    class VClock:
+        t = 0.0
+
+        def __call__(self):
+            return self.t
+    clock = VClock()
+    eng = serve.Engine(OracleBackend(wl.r, 1 << 22), 1 << 22, wl.chunk, wl.period, clock=clock)
+    for i, rd in enumerate(wl.reads):
+        eng.submit(i, rd.arrival, rd.events, rd.r_off, rd.r_len)
+    while not eng.all_done():
+        if eng.tick() == 0:
+            clock.t = eng.next_event_time()
+    return eng
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_serving_loop_matches_oracle_engine(L, use_graph):
+    """The serving loop on the GPU (real clock, time-compressed arrivals,
+    graph-replayed or eager ticks) returns for every read and chunk exactly
+    what the oracle-backed engine returns, whatever the tick batching."""
+    from paper_2310_05037_amd import serve
+    wl = W.serving_workload(60, rate=200.0, chunk=400, max_chunks=4, max_cands=8, ref_bases=200_000,
+                            period=1.0, seed_index=33)
+    _say(f"  gpu: serving reads={len(wl.reads)} graph={use_graph}")
+    eng, st = serve.serve(wl, arena_bytes=64 << 20, time_scale=0.02, use_graph=use_graph, max_jobs=1024,
+                          max_reads=128, timeout=120)
+    print("serving", st)
+    ref = _oracle_engine(wl)
+    assert st["failed"] == 0 and st["ticks"] > 0
+    for a, b in zip(eng.reads, ref.reads):
+        assert a.status == b.status and len(a.results) == len(b.results), a.rid
+        for x, y in zip(a.results, b.results):
+            assert x[0] == y[0] and x[1] == y[1] and x[2] == y[2]
+            assert np.array_equal(x[3].view(np.uint32), y[3].view(np.uint32)) and np.array_equal(x[4], y[4])
