@@ -5,11 +5,13 @@ batch (query lengths log-normal, median 1,500 events; regions 1.2-3.0x the
 query; 1-50 candidates per read): device-side planning (routing,
 longest-first ordering) plus the DTW kernels, inputs resident in HBM.  The
 timed path is the persistent, tuned form; the plain batched form (static
-assignment, arrival order) is timed on the same inputs beside it.
+assignment, arrival order) is timed on the same inputs beside it.  A
+serving leg then streams reads at a fixed arrival rate in 400-event chunks
+through resident rows and reports the p50/p99 chunk latency.
 
 Prints one JSON line (see the keys below).  --gpus above 1 is refused: the
 library runs on one GPU; pairs are independent, so a multi-GPU run would
-split the batch.
+split the batch by cells, one share per GPU.
 """
 from __future__ import annotations
 
@@ -47,6 +49,15 @@ def route_cells(b):
     return {"lo": int(cells[lo].sum()), "hi": int(cells[hi].sum()), "long": int(cells[long_].sum())}
 
 
+def route_bytes(b):
+    """Algorithmic HBM bytes per route: every pair reads its query and region
+    once and writes a score and an end (4n + 4m + 8)."""
+    m = b.r_len.astype(np.int64)
+    by = 4 * b.q_len.astype(np.int64) + 4 * m + 8
+    return {"lo": int(by[m <= 2048].sum()), "hi": int(by[(m > 2048) & (m <= 4096)].sum()),
+            "long": int(by[m > 4096].sum())}
+
+
 def cpu_baseline(b, seconds: float):
     """The CPU oracle (double precision, threaded over pairs) on a random
     sample of pairs until about `seconds` of work has run."""
@@ -71,6 +82,66 @@ def cpu_baseline(b, seconds: float):
             "sample": f"{done_pairs} random pairs ({done_cells:.3e} cells, {dt:.1f} s), float64 recurrence"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_multi_config2_traffic.txt")
+KERNEL_SOURCES = ["dtw_device.h", "dtw_multi.hip", "internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_05037_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration),
+    or None when the summary is missing or the kernel sources changed since
+    the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split("=", 1) for line in fh.read().splitlines() if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_calibration(mib: int):
+    """A plain copy kernel of known size (reads and writes `mib` MiB), for
+    scaling the FETCH_SIZE and WRITE_SIZE counters to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
+
+
+def serving_leg(n_reads: int, rate: float):
+    """Read Until serving at a fixed arrival rate, in real time: 400-event
+    chunks one second apart, up to 10 chunks and 1-50 candidates per read,
+    resident rows in an 8 GiB arena, one captured graph replayed per tick.
+    A short time-compressed run first warms up the graph and caches."""
+    from paper_2310_05037_amd import serve, workloads
+    warm = workloads.serving_workload(300, rate=rate, seed_index=103)
+    serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120)
+    wl = workloads.serving_workload(n_reads, rate=rate)
+    _, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600)
+    keep = ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "reads", "ticks", "jobs", "mapped", "unmapped",
+            "failed", "peak_arena_bytes", "wall_s", "gcups", "chunks_per_s")
+    out = {k: st[k] for k in keep}
+    out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period,
+                "latency": "decision on host minus the moment the chunk was available"})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,10 +151,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="time only the tuned path (for profiling runs)")
     ap.add_argument("--opts", type=str, default="", help="JSON dict of rawalign_opts fields for the tuned path")
+    ap.add_argument("--serving-reads", type=int, default=20000, help="reads in the serving leg (0: skip it)")
+    ap.add_argument("--serving-rate", type=float, default=2000.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a copy kernel of this size (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (pairs are independent: "
-              "a multi-GPU run would split the batch, see DESIGN.md)", file=sys.stderr)
+              "a multi-GPU run would split the batch by cells, one share per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -124,17 +202,27 @@ def main():
     gcups = cells / step_s / 1e9
     plain_gcups = plain_s = None
     pkt = {}
+    variants = {}
     if not args.skip_plain:
         plain_s, pkt = timed(plain_opts, max(2, args.steps // 2), 1)
         plain_gcups = cells / plain_s / 1e9
+        # Same batch with the anti-diagonal kernel for the regions above one
+        # stripe (the lane-striped kernels keep the shorter ones).
+        ad_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_ANTIDIAG)
+        ad_s, akt = timed(ad_opts, 2, 1)
+        variants["long_antidiag"] = {"value": cells / ad_s / 1e9, "unit": "GCUPS", "ms_per_step": ad_s * 1e3,
+                                     "kernels_ms": akt, "long_route_gcups": rc["long"] / akt["long_ms"] / 1e6,
+                                     "kernel": "k_antidiag"}
 
     # dominant kernel: the route with the largest average duration
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}
     dom = max(names, key=lambda k: kt[k])
     dom_cells = rc[names[dom]]
     achieved = VALU_OPS_PER_CELL * dom_cells / (kt[dom] / 1e3)
+    traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
-                "frac": achieved / valu_peak, "traffic": None,
+                "frac": achieved / valu_peak, "traffic": traffic,
+                "algorithmic_bytes": route_bytes(b)[names[dom]],
                 "kernel": {"lo_ms": "k_single<1..8>", "hi_ms": "k_single<9..16>", "long_ms": "k_multi"}[dom],
                 "kernel_avg_ms": kt[dom], "kernel_cells": dom_cells,
                 "ops_per_cell": VALU_OPS_PER_CELL,
@@ -161,10 +249,15 @@ def main():
         {"value": plain_gcups, "unit": "GCUPS", "ms_per_step": plain_s * 1e3, "kernels_ms": pkt},
         "persistent_over_plain": None if plain_gcups is None else gcups / plain_gcups,
         "kernels_ms": kt,
+        "variants": variants,
         "roofline": roofline,
         "serving": None,
         "cpu_baseline": None,
     }
+    del db
+    torch.cuda.empty_cache()
+    if args.serving_reads > 0:
+        out["serving"] = serving_leg(args.serving_reads, args.serving_rate)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -71,7 +71,8 @@ extern "C" {
 
 /* Kernels for regions longer than one stripe (4096 levels). */
 #define RAWALIGN_LONG_STRIPED 0     /* one wave sweeps the stripes in turn, edges through device memory */
-#define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup sweeps anti-diagonals, 3 diagonals in LDS */
+#define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup per pair sweeps anti-diagonals of 256-row blocks through LDS;
+                                       plain batches only (rawalign_dtw_extend rejects it) */
 
 /* opts.flags */
 #define RAWALIGN_FLAG_TIMING 1      /* record hipEvents around every kernel (rawalign_last_timing) */
@@ -81,7 +82,7 @@ typedef struct rawalign_opts {
     int32_t long_kernel;        /* RAWALIGN_LONG_* */
     int32_t lo_waves_per_cu;    /* persistent grid of the <= 2048-level kernel, per CU (0 = occupancy limit) */
     int32_t hi_waves_per_cu;    /* same, 2049..4096 levels */
-    int32_t long_waves_per_cu;  /* same, > 4096 levels */
+    int32_t long_waves_per_cu;  /* same, > 4096 levels (anti-diagonal kernel: workgroups per CU, 0 = 4) */
     int32_t streams;            /* 1: the three kernels run one after another on `stream`;
                                    3: concurrently on internal streams joined back to `stream` */
     int32_t flags;              /* RAWALIGN_FLAG_* */

@@ -1,5 +1,5 @@
 // Internal interface between the C ABI (rawalign_abi.cpp) and the kernels
-// (dtw_single.hip, dtw_multi.hip, dtw_plan.hip).  Not installed; the public
+// (dtw_single.hip, dtw_multi.hip, dtw_antidiag.hip, dtw_plan.hip).  Not installed; the public
 // interface is include/rawalign.h.
 #pragma once
 
@@ -34,6 +34,7 @@ struct PlanScratch {
     int32_t *list;      // [kNumRoutes * capacity] pair indices per route
     int64_t capacity;   // pairs the lists can hold
     float *edge;        // [multi_grid * kEdgeCap] stripe edge columns, one slot per wave
+    float *rowbuf;      // [antidiag_grid * kMaxRegion] anti-diagonal kernel row buffers (or null)
 };
 
 struct PairArrays {
@@ -59,6 +60,7 @@ struct LaunchCfg {
     int lo_grid;        // grid sizes (workgroups of one wave)
     int hi_grid;
     int multi_grid;     // also the number of edge slots
+    int antidiag_grid;  // workgroups of the anti-diagonal kernel (256 threads)
 };
 
 hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
@@ -69,6 +71,8 @@ hipError_t launch_single_hi(const PairArrays &a, int64_t n_pairs, const LaunchCf
                             const PlanScratch &s, hipStream_t stream);
 hipError_t launch_multi(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
                         const PlanScratch &s, hipStream_t stream);
+hipError_t launch_antidiag(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
+                           const PlanScratch &s, hipStream_t stream);
 hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
                          int32_t *out_best, double *out_score, uint8_t *out_mapped, hipStream_t stream);
@@ -77,5 +81,6 @@ hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *can
 int single_lo_blocks_per_cu(bool extend);
 int single_hi_blocks_per_cu(bool extend);
 int multi_blocks_per_cu(bool extend);
+int antidiag_blocks_per_cu();
 
 }  // namespace ra

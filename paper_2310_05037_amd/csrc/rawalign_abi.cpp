@@ -2,6 +2,7 @@
 // argument checks, per-stream scratch, launch order, tuning cache, timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -50,6 +51,8 @@ struct StreamScratch {
     int64_t capacity = 0;
     float *edge = nullptr;
     int64_t edge_slots = 0;
+    float *rowbuf = nullptr;    // anti-diagonal kernel only
+    int64_t row_slots = 0;
     hipStream_t sub[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr;
     hipEvent_t join[3] = {nullptr, nullptr, nullptr};
@@ -90,8 +93,8 @@ int alloc_fail(hipError_t e) {
     return fail(RAWALIGN_ENOMEM, std::string("scratch allocation: ") + hipGetErrorString(e));
 }
 
-int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots, bool timing, bool streams,
-                StreamScratch *&out) {
+int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots, int64_t row_slots, bool timing,
+                bool streams, StreamScratch *&out) {
     std::lock_guard<std::mutex> lk(g_mu);
     StreamScratch &s = g_scratch[{dev, stream}];
     hipError_t e;
@@ -127,6 +130,17 @@ int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots
         }
         s.edge_slots = edge_slots;
     }
+    if (s.row_slots < row_slots) {
+        if (s.rowbuf) (void)hipFree(s.rowbuf);
+        s.rowbuf = nullptr;
+        s.row_slots = 0;
+        e = hipMalloc((void **)&s.rowbuf, (size_t)row_slots * ra::kMaxRegion * sizeof(float));
+        if (e != hipSuccess) {
+            s.rowbuf = nullptr;
+            return alloc_fail(e);
+        }
+        s.row_slots = row_slots;
+    }
     if (streams && !s.sub[0]) {
         for (int i = 0; i < 3; ++i) {
             e = hipStreamCreateWithFlags(&s.sub[i], hipStreamNonBlocking);
@@ -155,15 +169,14 @@ ra::PlanScratch plan_view(StreamScratch &s) {
     p.list = s.list;
     p.capacity = s.capacity;
     p.edge = s.edge;
+    p.rowbuf = s.rowbuf;
     return p;
 }
 
 int check_opts(const rawalign_opts &o) {
     if (o.mode != RAWALIGN_MODE_PLAIN && o.mode != RAWALIGN_MODE_PERSISTENT)
         return fail(RAWALIGN_EINVAL, "opts.mode must be RAWALIGN_MODE_PLAIN or RAWALIGN_MODE_PERSISTENT");
-    if (o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
-        return fail(RAWALIGN_EINVAL, "opts.long_kernel RAWALIGN_LONG_ANTIDIAG is not available in this build");
-    if (o.long_kernel != RAWALIGN_LONG_STRIPED)
+    if (o.long_kernel != RAWALIGN_LONG_STRIPED && o.long_kernel != RAWALIGN_LONG_ANTIDIAG)
         return fail(RAWALIGN_EINVAL, "opts.long_kernel must be RAWALIGN_LONG_STRIPED or RAWALIGN_LONG_ANTIDIAG");
     const int32_t w[3] = {o.lo_waves_per_cu, o.hi_waves_per_cu, o.long_waves_per_cu};
     for (int32_t v : w)
@@ -224,6 +237,8 @@ int run(const Call &c, const rawalign_opts &o) {
     if (rc) return rc;
     rc = check_opts(o);
     if (rc) return rc;
+    if (c.rows && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
+        return fail(RAWALIGN_EINVAL, "extend: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
     if (c.n_pairs == 0) return RAWALIGN_OK;
     int dev = 0;
     DeviceInfo info;
@@ -236,11 +251,17 @@ int run(const Call &c, const rawalign_opts &o) {
     cfg.lo_grid = grid_of(info.cus, o.lo_waves_per_cu, ra::single_lo_blocks_per_cu(ext));
     cfg.hi_grid = grid_of(info.cus, o.hi_waves_per_cu, ra::single_hi_blocks_per_cu(ext));
     cfg.multi_grid = grid_of(info.cus, o.long_waves_per_cu, ra::multi_blocks_per_cu(ext));
+    // Anti-diagonal kernel: opts.long_waves_per_cu counts its workgroups per
+    // CU; by default at most 4, since each holds a 256 KiB row buffer.
+    const int ad_occ = ra::antidiag_blocks_per_cu();
+    cfg.antidiag_grid = info.cus * std::min(o.long_waves_per_cu ? o.long_waves_per_cu : 4, ad_occ);
+    const bool antidiag = o.long_kernel == RAWALIGN_LONG_ANTIDIAG;
 
     const bool timing = (o.flags & RAWALIGN_FLAG_TIMING) != 0;
     const bool concurrent = o.streams == 3;
     StreamScratch *s = nullptr;
-    rc = get_scratch(dev, c.stream, c.n_pairs, cfg.multi_grid, timing, concurrent, s);
+    rc = get_scratch(dev, c.stream, c.n_pairs, cfg.multi_grid, antidiag ? cfg.antidiag_grid : 0, timing, concurrent,
+                     s);
     if (rc) return rc;
 
     ra::PairArrays a;
@@ -276,8 +297,10 @@ int run(const Call &c, const rawalign_opts &o) {
     // Longest regions first: they bound the makespan.
     typedef hipError_t (*Launch)(const ra::PairArrays &, int64_t, const ra::LaunchCfg &, const ra::PlanScratch &,
                                  hipStream_t);
-    const Launch launches[3] = {ra::launch_multi, ra::launch_single_hi, ra::launch_single_lo};
-    const char *names[3] = {"multi-stripe kernel", "single-stripe kernel (36-64 columns per lane)",
+    const Launch launches[3] = {antidiag ? ra::launch_antidiag : ra::launch_multi, ra::launch_single_hi,
+                                ra::launch_single_lo};
+    const char *names[3] = {antidiag ? "anti-diagonal kernel" : "multi-stripe kernel",
+                            "single-stripe kernel (36-64 columns per lane)",
                             "single-stripe kernel (4-32 columns per lane)"};
     const int ev_slot[3] = {6, 4, 2};   // long, hi, lo
     for (int i = 0; i < 3; ++i) {

@@ -65,6 +65,16 @@ def test_argument_errors_without_device(L):
     o.long_waves_per_cu = 99
     rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
     assert rc == L.RAWALIGN_EINVAL and b"waves_per_cu" in so.rawalign_last_error()
+    o = L.opts_default()
+    o.long_kernel = 7
+    rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
+    # the anti-diagonal kernel runs plain batches only, not the streaming extension
+    o = L.opts_default()
+    o.long_kernel = L.LONG_ANTIDIAG
+    rc = so.rawalign_dtw_extend(fake, 10, fake, fake, fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake,
+                                None, ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
     # extend without a row arena
     rc = so.rawalign_dtw_extend(fake, 10, fake, fake, fake, 10, fake, fake, None, 0, fake, fake, 2, fake, fake,
                                 None, None)

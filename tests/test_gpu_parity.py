@@ -139,9 +139,45 @@ def test_long_regions_multi_stripe(L):
     s, e = _run(L, b)
     st = parity.check(b, s, e)
     print("long", st)
-    for kw in ({"streams": 3}, {"long_waves_per_cu": 2}, {"plain": True}):
+    for kw in ({"streams": 3}, {"long_waves_per_cu": 2}, {"plain": True}, {"long_kernel": L.LONG_ANTIDIAG},
+               {"long_kernel": L.LONG_ANTIDIAG, "mode": L.MODE_PLAIN}):
         s2, e2 = _run(L, b, **kw)
         assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2), kw
+
+
+def test_antidiag_kernel_against_oracle(L):
+    """The anti-diagonal kernel on its own: queries around its row-block
+    sizes (256 threads x 1, 2 or 4 rows, chosen at 512 and 2048 events) and
+    several blocks, regions just above one stripe up to the maximum, against
+    the float oracle bit for bit."""
+    from oracle import oracle
+    rng = np.random.default_rng(5)
+    ns = [1, 2, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4096, 4097, 8193, 16384, 3, 700]
+    ms = [4097, 4098, 5000, 4097, 9000, 4500, 4200, 6000, 4300, 4100, 5000, 4500, 4200, 7000, 4500, 4200, 4300,
+          4100, 65536, 20000]
+    reads = [rng.standard_normal(n).astype(np.float32) for n in ns]
+    r = rng.standard_normal(sum(ms)).astype(np.float32)
+    pairs, off = [], 0
+    for i, m in enumerate(ms):
+        pairs.append((i, off, m, False))
+        off += m
+    b = W._pack("antidiag", reads, pairs, r, {})
+    s, e = _run(L, b, long_kernel=L.LONG_ANTIDIAG)
+    for p in range(b.n_pairs):
+        q = b.q[b.q_off[p]:b.q_off[p] + b.q_len[p]]
+        rr = b.r[b.r_off[p]:b.r_off[p] + b.r_len[p]]
+        c32, e32 = oracle.dtw_f32(q, rr)
+        assert s[p].view(np.uint32) == np.float32(c32).view(np.uint32) and e[p] == e32, p
+    parity.check(b, s, e)
+
+
+def test_config4_antidiag_equals_striped(L):
+    """Full 1,024 x (10,000 x 20,000) batch: anti-diagonal and lane-striped
+    kernels give the same bits."""
+    b = W.config4()
+    s, e = _run(L, b)
+    s2, e2 = _run(L, b, long_kernel=L.LONG_ANTIDIAG)
+    assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2)
 
 
 def test_long_query_limit(L):
