@@ -315,7 +315,8 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
 // use S = ceil(m / 4096) and the smallest k with S * 256k >= m; then every
 // stripe starts inside the region ((S-1)*64*C < m for S <= 16).
 RA_DEV void stripe_shape(int m, int &S, int &k) {
-    S = (m + kShortMaxRegion - 1) / kShortMaxRegion;
+    const int width = m <= kSingleMaxRegion ? kSingleMaxRegion : 256 * kMultiMaxK;
+    S = (m + width - 1) / width;
     if (S < 1) S = 1;
     k = (m + 256 * S - 1) / (256 * S);
 }

@@ -6,6 +6,13 @@
 
 namespace ra {
 
+// Two independent min-plus chains per lane (the lane's two column halves one
+// row apart); the skew per stripe grows from 64 to 128 steps.
+#ifndef RA_MULTI_ILP2
+#define RA_MULTI_ILP2 1
+#endif
+constexpr bool kMultiIlp2 = RA_MULTI_ILP2 != 0;
+
 template <int C, bool EXT>
 RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int &bj) {
     best = kInf;
@@ -15,9 +22,9 @@ RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int 
         float b, nc;
         int j;
         if (s == 0)
-            sweep<C, EXT, false, true, true>(pv, 0, edge, 0.0f, nc, b, j);
+            sweep<C, EXT, false, true, kMultiIlp2>(pv, 0, edge, 0.0f, nc, b, j);
         else
-            sweep<C, EXT, true, true, true>(pv, s * 64 * C, edge, corner, nc, b, j);
+            sweep<C, EXT, true, true, kMultiIlp2>(pv, s * 64 * C, edge, corner, nc, b, j);
         corner = nc;
         take_min(best, bj, b, j);
         // Lane 63's edge stores must be visible to lane 0 of the next stripe.
@@ -26,9 +33,34 @@ RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int 
     }
 }
 
-// Columns per lane C = 4k, k in 9..16 for every multi-stripe region.
+// Waves per SIMD the register budget of the widest stripe allows.
+constexpr int kMultiWaves = kMultiMaxK <= 12 ? 3 : 2;
+
+// Narrowest stripe any region above one stripe gets from stripe_shape: the
+// smallest ceil(m / (256 S)) over m in (kSingleMaxRegion, kMaxRegion].
+constexpr int multi_min_k() {
+    int kmin = kMultiMaxK;
+    for (int m = kSingleMaxRegion + 1; m <= kMaxRegion; ++m) {
+        const int w = 256 * kMultiMaxK;
+        const int S = (m + w - 1) / w;
+        const int k = (m + 256 * S - 1) / (256 * S);
+        if (k < kmin) kmin = k;
+    }
+    return kmin;
+}
+constexpr int kMultiMinK = multi_min_k();
+static_assert(kMultiMinK >= 5, "multi-stripe kernel instantiates k >= 5");
+
+template <int K, bool EXT>
+RA_DEV void multi_case(int k, const PairView &pv, int S, float *edge, float &best, int &bj) {
+    if constexpr (K >= kMultiMinK && K <= kMultiMaxK) {
+        if (k == K) multi_pair<4 * K, EXT>(pv, S, edge, best, bj);
+    }
+}
+
+// Columns per lane C = 4k, k in kMultiMinK..kMultiMaxK for every multi-stripe region.
 template <bool EXT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMultiWaves, kMultiWaves)))
 void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
              int32_t *queue, float *edge_base) {
     float *edge = edge_base + (size_t)blockIdx.x * kEdgeCap;
@@ -46,10 +78,18 @@ void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__re
         stripe_shape(pv.m, S, k);
         float best = __builtin_nanf("");
         int bj = -2;
-#define RA_CASE(K) \
-    if (k == K) multi_pair<4 * K, EXT>(pv, S, edge, best, bj);
-        RA_CASE(9) RA_CASE(10) RA_CASE(11) RA_CASE(12) RA_CASE(13) RA_CASE(14) RA_CASE(15) RA_CASE(16)
-#undef RA_CASE
+        multi_case<5, EXT>(k, pv, S, edge, best, bj);
+        multi_case<6, EXT>(k, pv, S, edge, best, bj);
+        multi_case<7, EXT>(k, pv, S, edge, best, bj);
+        multi_case<8, EXT>(k, pv, S, edge, best, bj);
+        multi_case<9, EXT>(k, pv, S, edge, best, bj);
+        multi_case<10, EXT>(k, pv, S, edge, best, bj);
+        multi_case<11, EXT>(k, pv, S, edge, best, bj);
+        multi_case<12, EXT>(k, pv, S, edge, best, bj);
+        multi_case<13, EXT>(k, pv, S, edge, best, bj);
+        multi_case<14, EXT>(k, pv, S, edge, best, bj);
+        multi_case<15, EXT>(k, pv, S, edge, best, bj);
+        multi_case<16, EXT>(k, pv, S, edge, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

@@ -22,7 +22,7 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
     const int64_t qo = a.q_off[p];
     const int64_t ro = a.r_off[p];
     bool ok = n >= 0 && m >= 0 && qo >= 0 && ro >= 0 && qo + n <= a.q_size && ro + m <= a.r_size &&
-              m <= kMaxRegion && n <= kMaxQuery && (m <= kShortMaxRegion || n <= kEdgeCap);
+              m <= kMaxRegion && n <= kMaxQuery && (m <= kSingleMaxRegion || n <= kEdgeCap);
     bool fresh = true;
     if (pa.extend) {
         const int64_t wo = a.row_off[p];
@@ -46,7 +46,7 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
     }
     int route;
     if (m <= kSingleLoMaxRegion) route = kRouteSingleLo;
-    else if (m <= kShortMaxRegion) route = kRouteSingleHi;
+    else if (m <= kSingleMaxRegion) route = kRouteSingleHi;
     else route = kRouteMulti;
     bucket = 0;
     if (pa.buckets > 1) {

@@ -1,13 +1,19 @@
-// dtw_single.hip -- regions of at most 4096 levels: one wave sweeps the
-// whole region as a single stripe (see dtw_device.h for the layout).
+// dtw_single.hip -- regions of at most kSingleMaxRegion levels: one wave
+// sweeps the whole region as a single stripe (see dtw_device.h for the
+// layout).
 #include "dtw_device.h"
 
 namespace ra {
 
 // C = 4k columns per lane for k in [KLO, KHI]; at most 32 columns fit 128
-// VGPRs (4 waves per SIMD), up to 64 columns fit 256 (2 waves per SIMD).
+// VGPRs (4 waves per SIMD), 44 fit 168 (3 waves), 64 fit 256 (2 waves).
+template <int KHI>
+constexpr int single_waves() {
+    return KHI <= 8 ? 4 : (KHI <= 11 ? 3 : 2);
+}
+
 template <bool EXT, int KLO, int KHI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KHI <= 8 ? 4 : 2, KHI <= 8 ? 4 : 2)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(single_waves<KHI>(), single_waves<KHI>())))
 void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
               int32_t *queue) {
     const int n_items = *count;
@@ -62,7 +68,7 @@ hipError_t launch_single_lo(const PairArrays &a, int64_t n_pairs, const LaunchCf
 
 hipError_t launch_single_hi(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
                             hipStream_t stream) {
-    return launch_single<9, 16>(kRouteSingleHi, cfg.hi_grid, a, n_pairs, cfg, s, stream);
+    return launch_single<9, kSingleHiMaxK>(kRouteSingleHi, cfg.hi_grid, a, n_pairs, cfg, s, stream);
 }
 
 template <bool EXT, int KLO, int KHI>
@@ -77,7 +83,7 @@ int single_lo_blocks_per_cu(bool extend) {
 }
 
 int single_hi_blocks_per_cu(bool extend) {
-    return extend ? blocks_per_cu<true, 9, 16>() : blocks_per_cu<false, 9, 16>();
+    return extend ? blocks_per_cu<true, 9, kSingleHiMaxK>() : blocks_per_cu<false, 9, kSingleHiMaxK>();
 }
 
 }  // namespace ra

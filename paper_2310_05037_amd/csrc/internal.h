@@ -20,6 +20,22 @@ constexpr int kShortMaxRegion = 64 * kMaxColsPerLane;  // 4096: one stripe
 constexpr int kSingleLoMaxRegion = 2048;               // 64 lanes x 32 columns
 constexpr int kMaxStripes = 16;
 constexpr int kMaxRegion = kMaxStripes * kShortMaxRegion;   // 65536
+// Widest region the single-stripe kernel takes, in groups of 4 columns per
+// lane (16: 4096 levels at two waves per SIMD; 11: 2816 levels at three).
+#ifndef RA_SINGLE_HI_KMAX
+#define RA_SINGLE_HI_KMAX 16
+#endif
+constexpr int kSingleHiMaxK = RA_SINGLE_HI_KMAX;
+constexpr int kSingleMaxRegion = 256 * kSingleHiMaxK;
+static_assert(kSingleHiMaxK >= 9 && kSingleHiMaxK <= 16, "single-stripe width");
+// Widest stripe of the multi-stripe kernel, in groups of 4 columns per lane
+// (16: 4096 columns, two waves per SIMD; 11: 2816 columns, three waves per
+// SIMD, which issues faster despite the extra stripe boundaries).
+#ifndef RA_MULTI_KMAX
+#define RA_MULTI_KMAX 11
+#endif
+constexpr int kMultiMaxK = RA_MULTI_KMAX;
+static_assert(kMultiMaxK >= 9 && kMultiMaxK <= 16, "multi-stripe width");
 constexpr int kMaxQuery = 1 << 28;                     // keeps 4*n and the step counter in int
 constexpr int kEdgeCap = 16384;                        // longest query of a multi-stripe pair
 

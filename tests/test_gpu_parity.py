@@ -256,3 +256,23 @@ def test_decide_matches_oracle(L):
         assert np.array_equal(ob.cpu().numpy(), rb)
         assert np.array_equal(os_.cpu().numpy(), rs)
         assert np.array_equal(om.cpu().numpy(), rm)
+
+
+def test_autotune_and_tuning_cache(L, tmp_path):
+    """The autotuner picks a valid setting, writes it to a cache that loads
+    back to the same setting, and the tuned path (opts NULL) gives the same
+    bits as the defaults."""
+    b = W.config1(n_pairs=1500)
+    db = L.DeviceBatch(b)
+    _say(f"  gpu: autotune {b.name} pairs={b.n_pairs}")
+    db.run(opts=L.make_opts())
+    s0, e0 = db.results()
+    cache = str(tmp_path / "tune.json")
+    best = L.rawalign_autotune(*db.args(), cache_path=cache)
+    assert best.mode == L.MODE_PERSISTENT and best.streams in (1, 3)
+    loaded = L.rawalign_load_tuning(cache)
+    assert loaded.as_dict() == best.as_dict()
+    db.score.fill_(-1.0)
+    db.run()   # opts NULL: the tuned setting
+    s1, e1 = db.results()
+    assert np.array_equal(s0.view(np.uint32), s1.view(np.uint32)) and np.array_equal(e0, e1)
