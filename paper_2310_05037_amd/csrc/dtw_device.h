@@ -310,15 +310,16 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
     wave_min(best, bj);
 }
 
-// Stripe shape of a region of m levels: S stripes of 64*C columns, C = 4k.
-// Single-stripe pairs use the smallest k with 256k >= m.  Multi-stripe pairs
-// use S = ceil(m / 4096) and the smallest k with S * 256k >= m; then every
-// stripe starts inside the region ((S-1)*64*C < m for S <= 16).
-RA_DEV void stripe_shape(int m, int &S, int &k) {
+// Stripe shape of a region of m levels: S stripes of 64*C columns, C = 2h
+// (h column pairs per lane).  Single-stripe pairs use the smallest h with
+// 128h >= m.  Multi-stripe pairs use S = ceil(m / (256 kMultiMaxK)) and the
+// smallest h with S * 128h >= m; then every stripe starts inside the region
+// ((S-1)*64*C < m over the whole range of m).
+RA_DEV void stripe_shape(int m, int &S, int &h) {
     const int width = m <= kSingleMaxRegion ? kSingleMaxRegion : 256 * kMultiMaxK;
     S = (m + width - 1) / width;
     if (S < 1) S = 1;
-    k = (m + 256 * S - 1) / (256 * S);
+    h = (m + 128 * S - 1) / (128 * S);
 }
 
 }  // namespace ra

@@ -37,28 +37,31 @@ RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int 
 constexpr int kMultiWaves = kMultiMaxK <= 12 ? 3 : 2;
 
 // Narrowest stripe any region above one stripe gets from stripe_shape: the
-// smallest ceil(m / (256 S)) over m in (kSingleMaxRegion, kMaxRegion].
-constexpr int multi_min_k() {
-    int kmin = kMultiMaxK;
+// smallest h = ceil(m / (128 S)) over m in (kSingleMaxRegion, kMaxRegion].
+constexpr int multi_min_h() {
+    int hmin = 2 * kMultiMaxK;
     for (int m = kSingleMaxRegion + 1; m <= kMaxRegion; ++m) {
         const int w = 256 * kMultiMaxK;
         const int S = (m + w - 1) / w;
-        const int k = (m + 256 * S - 1) / (256 * S);
-        if (k < kmin) kmin = k;
+        const int h = (m + 128 * S - 1) / (128 * S);
+        if (h < hmin) hmin = h;
     }
-    return kmin;
+    return hmin;
 }
-constexpr int kMultiMinK = multi_min_k();
-static_assert(kMultiMinK >= 5, "multi-stripe kernel instantiates k >= 5");
+constexpr int kMultiMinH = multi_min_h();
+constexpr int kMultiMaxH = 2 * kMultiMaxK;
 
-template <int K, bool EXT>
-RA_DEV void multi_case(int k, const PairView &pv, int S, float *edge, float &best, int &bj) {
-    if constexpr (K >= kMultiMinK && K <= kMultiMaxK) {
-        if (k == K) multi_pair<4 * K, EXT>(pv, S, edge, best, bj);
+// Columns per lane C = 2H for every H in [kMultiMinH, kMultiMaxH].
+template <int H, bool EXT>
+RA_DEV void multi_dispatch(int h, const PairView &pv, int S, float *edge, float &best, int &bj) {
+    if constexpr (H <= kMultiMaxH) {
+        if (h == H)
+            multi_pair<2 * H, EXT>(pv, S, edge, best, bj);
+        else
+            multi_dispatch<H + 1, EXT>(h, pv, S, edge, best, bj);
     }
 }
 
-// Columns per lane C = 4k, k in kMultiMinK..kMultiMaxK for every multi-stripe region.
 template <bool EXT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMultiWaves, kMultiWaves)))
 void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
@@ -74,22 +77,11 @@ void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__re
     while (item < n_items) {
         const int p = list[item];
         const PairView pv = pair_view<EXT>(a, p);
-        int S, k;
-        stripe_shape(pv.m, S, k);
+        int S, h;
+        stripe_shape(pv.m, S, h);
         float best = __builtin_nanf("");
         int bj = -2;
-        multi_case<5, EXT>(k, pv, S, edge, best, bj);
-        multi_case<6, EXT>(k, pv, S, edge, best, bj);
-        multi_case<7, EXT>(k, pv, S, edge, best, bj);
-        multi_case<8, EXT>(k, pv, S, edge, best, bj);
-        multi_case<9, EXT>(k, pv, S, edge, best, bj);
-        multi_case<10, EXT>(k, pv, S, edge, best, bj);
-        multi_case<11, EXT>(k, pv, S, edge, best, bj);
-        multi_case<12, EXT>(k, pv, S, edge, best, bj);
-        multi_case<13, EXT>(k, pv, S, edge, best, bj);
-        multi_case<14, EXT>(k, pv, S, edge, best, bj);
-        multi_case<15, EXT>(k, pv, S, edge, best, bj);
-        multi_case<16, EXT>(k, pv, S, edge, best, bj);
+        multi_dispatch<kMultiMinH, EXT>(h, pv, S, edge, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

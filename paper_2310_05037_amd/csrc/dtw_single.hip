@@ -5,13 +5,27 @@
 
 namespace ra {
 
-// C = 4k columns per lane for k in [KLO, KHI]; at most 32 columns fit 128
-// VGPRs (4 waves per SIMD), 44 fit 168 (3 waves), 64 fit 256 (2 waves).
+// At most 32 columns per lane fit 128 VGPRs (4 waves per SIMD), 44 fit 168
+// (3 waves), 64 fit 256 (2 waves).
 template <int KHI>
 constexpr int single_waves() {
     return KHI <= 8 ? 4 : (KHI <= 11 ? 3 : 2);
 }
 
+// Columns per lane C = 2H for H in [H, HMAX].
+template <bool EXT, int H, int HMAX>
+RA_DEV void single_dispatch(int h, const PairView &pv, float &best, int &bj) {
+    if constexpr (H <= HMAX) {
+        if (h == H) {
+            float nc;
+            sweep<2 * H, EXT, false, false, false>(pv, 0, nullptr, 0.0f, nc, best, bj);
+        } else {
+            single_dispatch<EXT, H + 1, HMAX>(h, pv, best, bj);
+        }
+    }
+}
+
+// Regions of 256(KLO-1)+1 .. 256 KHI levels.
 template <bool EXT, int KLO, int KHI>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(single_waves<KHI>(), single_waves<KHI>())))
 void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
@@ -26,15 +40,10 @@ void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__r
     while (item < n_items) {
         const int p = list[item];
         const PairView pv = pair_view<EXT>(a, p);
-        const int k = (pv.m + 255) >> 8;
+        const int h = (pv.m + 127) >> 7;   // column pairs per lane
         float best = __builtin_nanf("");
         int bj = -2;
-        float nc;
-#define RA_CASE(K) \
-    if (K >= KLO && K <= KHI && k == K) sweep<4 * K, EXT, false, false, false>(pv, 0, nullptr, 0.0f, nc, best, bj);
-        RA_CASE(1) RA_CASE(2) RA_CASE(3) RA_CASE(4) RA_CASE(5) RA_CASE(6) RA_CASE(7) RA_CASE(8)
-        RA_CASE(9) RA_CASE(10) RA_CASE(11) RA_CASE(12) RA_CASE(13) RA_CASE(14) RA_CASE(15) RA_CASE(16)
-#undef RA_CASE
+        single_dispatch<EXT, 2 * KLO - 1, 2 * KHI>(h, pv, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

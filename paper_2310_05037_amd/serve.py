@@ -439,16 +439,28 @@ def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_gra
     arena_floats = arena_bytes // 4
     if backend is None:
         backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph)
+    # The engine's clock starts at zero when the loop starts, after every read
+    # has been submitted (submitting many reads takes a while itself).
+    origin = [time.perf_counter()]
+
+    def clock():
+        return time.perf_counter() - origin[0]
+
     eng = Engine(backend, arena_floats, workload.chunk, workload.period * time_scale, max_jobs=max_jobs,
-                 max_reads=max_reads)
+                 max_reads=max_reads, clock=clock)
     if hasattr(backend, "prepare"):
         backend.prepare(eng.b_match, eng.threshold)   # capture before the clock starts
-    t0 = eng.clock()
     for i, rd in enumerate(workload.reads):
-        eng.submit(i, t0 + rd.arrival * time_scale, rd.events, rd.r_off, rd.r_len)
+        eng.submit(i, rd.arrival * time_scale, rd.events, rd.r_off, rd.r_len)
+    origin[0] = time.perf_counter()
     eng.run(timeout=timeout)
-    wall = eng.clock() - t0
+    wall = eng.clock()
     st = eng.stats()
+    # The five slowest chunks: (moment the chunk became available, relative
+    # to the start of the run, and its latency), in ms.
+    worst = sorted(eng.latencies, key=lambda x: -x[2])[:5]
+    st["worst_ms"] = [(round(eng.reads[rid].chunk_ready_time(c, eng.period) * 1e3, 3), round(lat * 1e3, 3))
+                      for rid, c, lat in worst]
     st.update({"wall_s": wall, "gcups": eng.cells / wall / 1e9, "chunks_per_s": st["chunks"] / wall,
                "time_scale": time_scale, "rate_reads_per_s": workload.rate / time_scale})
     return eng, st
