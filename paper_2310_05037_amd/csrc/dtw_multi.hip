@@ -7,9 +7,11 @@
 namespace ra {
 
 // Two independent min-plus chains per lane (the lane's two column halves one
-// row apart); the skew per stripe grows from 64 to 128 steps.
+// row apart); the skew per stripe grows from 64 to 128 steps.  Off by
+// default: at four waves per SIMD the other waves supply the independent
+// work and the shorter skew wins.
 #ifndef RA_MULTI_ILP2
-#define RA_MULTI_ILP2 1
+#define RA_MULTI_ILP2 0
 #endif
 constexpr bool kMultiIlp2 = RA_MULTI_ILP2 != 0;
 
@@ -34,7 +36,11 @@ RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int 
 }
 
 // Waves per SIMD the register budget of the widest stripe allows.
-constexpr int kMultiWaves = kMultiMaxK <= 12 ? 3 : 2;
+#ifdef RA_MULTI_WAVES
+constexpr int kMultiWaves = RA_MULTI_WAVES;
+#else
+constexpr int kMultiWaves = kMultiMaxK <= 8 ? 4 : (kMultiMaxK <= 12 ? 3 : 2);
+#endif
 
 // Narrowest stripe any region above one stripe gets from stripe_shape: the
 // smallest h = ceil(m / (128 S)) over m in (kSingleMaxRegion, kMaxRegion].

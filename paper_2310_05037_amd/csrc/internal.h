@@ -27,15 +27,15 @@ constexpr int kMaxRegion = kMaxStripes * kShortMaxRegion;   // 65536
 #endif
 constexpr int kSingleHiMaxK = RA_SINGLE_HI_KMAX;
 constexpr int kSingleMaxRegion = 256 * kSingleHiMaxK;
-static_assert(kSingleHiMaxK >= 9 && kSingleHiMaxK <= 16, "single-stripe width");
+static_assert(kSingleHiMaxK >= 8 && kSingleHiMaxK <= 16, "single-stripe width");
 // Widest stripe of the multi-stripe kernel, in groups of 4 columns per lane
-// (16: 4096 columns, two waves per SIMD; 11: 2816 columns, three waves per
+// (16: 4096 columns at two waves per SIMD; 8: 2048 columns at four waves per
 // SIMD, which issues faster despite the extra stripe boundaries).
 #ifndef RA_MULTI_KMAX
-#define RA_MULTI_KMAX 11
+#define RA_MULTI_KMAX 8
 #endif
 constexpr int kMultiMaxK = RA_MULTI_KMAX;
-static_assert(kMultiMaxK >= 9 && kMultiMaxK <= 16, "multi-stripe width");
+static_assert(kMultiMaxK >= 5 && kMultiMaxK <= 16, "multi-stripe width");
 constexpr int kMaxQuery = 1 << 28;                     // keeps 4*n and the step counter in int
 constexpr int kEdgeCap = 16384;                        // longest query of a multi-stripe pair
 
