@@ -178,6 +178,45 @@ int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off
                     int32_t *out_best, double *out_score, uint8_t *out_mapped, void *stream);
 
 /*
+ * Mapping with early termination (Sec. 2.4.1, branch and bound): the same
+ * per-read decision as rawalign_dtw_batch followed by rawalign_decide, with
+ * hopeless candidates dropped before their table is finished.
+ *   - Read k's candidates cand_off[k] .. cand_off[k]+cand_cnt[k]-1 are taken
+ *     to be in chaining-score order, best first.  Every read's first
+ *     candidate is queued ahead of all other pairs (longest first within
+ *     each group); one persistent kernel pulls pairs from that queue.
+ *   - A pair is swept block_rows query rows at a time through its resident
+ *     row rows[row_off[p] .. +r_len[p]) (scratch contents).  After a block
+ *     that ended at row i the cost of every path is at least min_j D(i, j)
+ *     (costs never decrease along a path), so the pair's Score
+ *     b_match * n_events[k] - C_DTW is at most b_match * n_events[k] -
+ *     min_j D(i, j); when that is strictly below the best Score its read has
+ *     reached so far, the pair is dropped: out_score = +inf, out_end = -3.
+ *     A completed pair raises its read's best (an atomic maximum).
+ *   - A dropped pair can neither win nor tie, so out_best, out_best_score
+ *     and out_mapped equal those of rawalign_decide on the scores of the full
+ *     computation; completed pairs' out_score/out_end equal
+ *     rawalign_dtw_batch's bit for bit.  Which pairs are dropped depends on
+ *     timing and can vary between runs.
+ *   - max_query: the longest q_len the caller passes; longer pairs get the
+ *     sentinel NaN, -2.  block_rows in [64, RAWALIGN_MAX_QUERY_LONG].  A
+ *     pair claimed by several reads, or by none, is aligned whole.  rows must
+ *     give every pair its own slot of r_len[p] floats.
+ *   - opts: long_waves_per_cu sets the persistent grid in waves per CU
+ *     (0 = occupancy limit, 16); other fields are not used.  NULL = defaults.
+ *   Other arguments, sentinels and limits as in rawalign_dtw_batch and
+ *   rawalign_decide.  Scratch (about 9 bytes per pair and 8 per read, plus
+ *   the stripe edge slots) is allocated per (device, stream) on first use.
+ */
+int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                     const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len, int64_t n_pairs,
+                     const int64_t *cand_off, const int32_t *cand_cnt, const int32_t *n_events, int64_t n_reads,
+                     double b_match, double threshold, int32_t max_query, int32_t block_rows,
+                     float *rows, int64_t rows_size, const int64_t *row_off,
+                     float *out_score, int32_t *out_end, int32_t *out_best, double *out_best_score,
+                     uint8_t *out_mapped, void *stream, const rawalign_opts *opts);
+
+/*
  * Autotuner: times candidate settings (persistent grid sizes of the three
  * kernels, concurrent or sequential kernels) on the caller's device batch
  * (same layout as rawalign_dtw_batch; out_score/out_end are scratch outputs)

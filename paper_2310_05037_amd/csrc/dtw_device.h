@@ -322,4 +322,37 @@ RA_DEV void stripe_shape(int m, int &S, int &h) {
     h = (m + 128 * S - 1) / (128 * S);
 }
 
+// Two independent min-plus chains per lane (the lane's two column halves one
+// row apart); the skew per stripe grows from 64 to 128 steps.  Off by
+// default: at four waves per SIMD the other waves supply the independent
+// work and the shorter skew wins.
+#ifndef RA_MULTI_ILP2
+#define RA_MULTI_ILP2 0
+#endif
+constexpr bool kMultiIlp2 = RA_MULTI_ILP2 != 0;
+
+// One pair swept stripe by stripe by one wave (several stripes when the
+// region is wider than one): lane 63 stores each stripe's last column into
+// the wave's edge slot, lane 0 of the next stripe reads it back.  Returns
+// the minimum of the pair's last row and its smallest column.
+template <int C, bool EXT>
+RA_DEV void multi_pair(const PairView &pv, int S, float *edge, float &best, int &bj) {
+    best = kInf;
+    bj = 0x7fffffff;
+    float corner = 0.0f;   // D(-1, col_base-1) of the next stripe
+    for (int s = 0; s < S; ++s) {
+        float b, nc;
+        int j;
+        if (s == 0)
+            sweep<C, EXT, false, true, kMultiIlp2>(pv, 0, edge, 0.0f, nc, b, j);
+        else
+            sweep<C, EXT, true, true, kMultiIlp2>(pv, s * 64 * C, edge, corner, nc, b, j);
+        corner = nc;
+        take_min(best, bj, b, j);
+        // Lane 63's edge stores must be visible to lane 0 of the next stripe.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
 }  // namespace ra

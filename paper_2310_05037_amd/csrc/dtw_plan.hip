@@ -72,18 +72,31 @@ __global__ void k_plan_zero(PlanScratch s) {
     }
 }
 
-__global__ void k_plan_count(PlanArgs pa) {
+constexpr int kPlanBlock = 256;
+constexpr int kBins = kNumRoutes * kBuckets;
+
+// Each workgroup counts its pairs per (route, bucket) in LDS and adds the
+// non-zero bins to the global histogram: one global atomic per bin per
+// workgroup instead of one per pair.
+__global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs pa) {
+    __shared__ int h[kBins];
+    for (int i = threadIdx.x; i < kBins; i += kPlanBlock) h[i] = 0;
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= pa.n_pairs) return;
-    int b = 0, e = 0;
-    float sc = 0.0f;
-    const int route = classify(pa, p, b, sc, e);
-    if (route >= 0) {
-        atomicAdd(&pa.s.hist[route * kBuckets + b], 1);
-    } else {
-        pa.a.out_score[p] = sc;
-        pa.a.out_end[p] = e;
+    if (p < pa.n_pairs) {
+        int b = 0, e = 0;
+        float sc = 0.0f;
+        const int route = classify(pa, p, b, sc, e);
+        if (route >= 0) {
+            atomicAdd(&h[route * kBuckets + b], 1);
+        } else {
+            pa.a.out_score[p] = sc;
+            pa.a.out_end[p] = e;
+        }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBins; i += kPlanBlock)
+        if (h[i]) atomicAdd(&pa.s.hist[i], h[i]);
 }
 
 // Exclusive scan of each route's histogram (bucket 0 first) -> cursors.
@@ -100,15 +113,31 @@ __global__ void k_plan_scan(PlanScratch s) {
     s.queue[route] = 0;
 }
 
-__global__ void k_plan_scatter(PlanArgs pa) {
+// Each workgroup ranks its pairs per bin in LDS, reserves one contiguous
+// range per bin with a single global atomic on the bin's cursor, and writes
+// its pairs there (in plain mode, one bin per route: workgroups keep their
+// order of arrival at the cursor, pairs inside a workgroup their LDS rank).
+__global__ __launch_bounds__(kPlanBlock) void k_plan_scatter(PlanArgs pa) {
+    __shared__ int cnt[kBins];
+    __shared__ int base[kBins];
+    for (int i = threadIdx.x; i < kBins; i += kPlanBlock) cnt[i] = 0;
+    __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= pa.n_pairs) return;
-    int b = 0, e = 0;
-    float sc = 0.0f;
-    const int route = classify(pa, p, b, sc, e);
-    if (route < 0) return;
-    const int pos = atomicAdd(&pa.s.hist[route * kBuckets + b], 1);
-    pa.s.list[route * pa.s.capacity + pos] = (int32_t)p;
+    int bin = -1, rank = 0, route = -1;
+    if (p < pa.n_pairs) {
+        int b = 0, e = 0;
+        float sc = 0.0f;
+        route = classify(pa, p, b, sc, e);
+        if (route >= 0) {
+            bin = route * kBuckets + b;
+            rank = atomicAdd(&cnt[bin], 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBins; i += kPlanBlock)
+        if (cnt[i]) base[i] = atomicAdd(&pa.s.hist[i], cnt[i]);
+    __syncthreads();
+    if (bin >= 0) pa.s.list[route * pa.s.capacity + base[bin] + rank] = (int32_t)p;
 }
 
 hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
@@ -119,11 +148,11 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
     pa.buckets = cfg.persistent ? kBuckets : 1;
     pa.extend = a.rows != nullptr;
     pa.s = s;
-    hipLaunchKernelGGL(k_plan_zero, dim3((kNumRoutes * kBuckets + 255) / 256), dim3(256), 0, stream, s);
-    const unsigned g = (unsigned)((n_pairs + 255) / 256);
-    hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(256), 0, stream, pa);
+    hipLaunchKernelGGL(k_plan_zero, dim3((kBins + 255) / 256), dim3(256), 0, stream, s);
+    const unsigned g = (unsigned)((n_pairs + kPlanBlock - 1) / kPlanBlock);
+    hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(kPlanBlock), 0, stream, pa);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
-    hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(256), 0, stream, pa);
+    hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(kPlanBlock), 0, stream, pa);
     return hipGetLastError();
 }
 

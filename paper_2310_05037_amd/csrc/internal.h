@@ -1,5 +1,5 @@
 // Internal interface between the C ABI (rawalign_abi.cpp) and the kernels
-// (dtw_single.hip, dtw_multi.hip, dtw_antidiag.hip, dtw_plan.hip).  Not installed; the public
+// (dtw_single.hip, dtw_multi.hip, dtw_antidiag.hip, dtw_plan.hip, dtw_bnb.hip).  Not installed; the public
 // interface is include/rawalign.h.
 #pragma once
 
@@ -71,6 +71,32 @@ struct PairArrays {
     const uint8_t *first_chunk;
 };
 
+// Early termination (branch and bound): pair status and scratch.
+enum BnbStatus : uint8_t { kBnbWaiting = 0, kBnbFirst = 1, kBnbDone = 2 };
+
+struct BnbScratch {
+    int32_t *read_of;     // [n_pairs] read owning the pair, -1 none, -2 several
+    uint8_t *status;      // [n_pairs] BnbStatus
+    uint64_t *best;       // [n_reads] best Score so far, order-preserving key
+    int32_t *list;        // [n_pairs] pairs to align: first candidates, then the others, longest first
+    int32_t *hist;        // [2 * kBuckets] histogram, then cursors
+    int32_t *counts;      // [2] pairs per group
+    int32_t *queue;       // work-queue head
+};
+
+struct BnbArgs {
+    PairArrays a;         // pairs, resident rows and final outputs
+    int64_t n_pairs;
+    const int64_t *cand_off;
+    const int32_t *cand_cnt;
+    const int32_t *n_events;
+    int64_t n_reads;
+    double b_match;
+    int max_query;
+    int block_rows;
+    BnbScratch s;
+};
+
 struct LaunchCfg {
     bool persistent;    // atomic queue + LPT order (else static assignment, arrival order)
     int lo_grid;        // grid sizes (workgroups of one wave)
@@ -89,6 +115,8 @@ hipError_t launch_multi(const PairArrays &a, int64_t n_pairs, const LaunchCfg &c
                         const PlanScratch &s, hipStream_t stream);
 hipError_t launch_antidiag(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
                            const PlanScratch &s, hipStream_t stream);
+hipError_t launch_bnb(const BnbArgs &b, int grid, float *edge, hipStream_t stream);
+int bnb_blocks_per_cu();
 hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
                          int32_t *out_best, double *out_score, uint8_t *out_mapped, hipStream_t stream);

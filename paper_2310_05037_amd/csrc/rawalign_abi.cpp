@@ -60,6 +60,14 @@ struct StreamScratch {
 };
 std::map<std::pair<int, hipStream_t>, StreamScratch> g_scratch;
 
+// Early-termination scratch, per (device, stream), grown on demand.
+struct BnbStore {
+    void *mem = nullptr;
+    int64_t pairs = 0, reads = 0;
+    ra::BnbScratch view;
+};
+std::map<std::pair<int, hipStream_t>, BnbStore> g_bnb;
+
 struct TimingRecord {
     hipEvent_t ev[8] = {};
     bool valid = false;
@@ -414,6 +422,119 @@ int rawalign_dtw_extend(const float *q, int64_t q_size, const int64_t *q_off, co
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_jobs, out_score, out_end,
            rows, rows_size, row_off, first_chunk, (hipStream_t)stream};
     return run(c, effective_opts(opts));
+}
+
+int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                     const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len, int64_t n_pairs,
+                     const int64_t *cand_off, const int32_t *cand_cnt, const int32_t *n_events, int64_t n_reads,
+                     double b_match, double threshold, int32_t max_query, int32_t block_rows,
+                     float *rows, int64_t rows_size, const int64_t *row_off,
+                     float *out_score, int32_t *out_end, int32_t *out_best, double *out_best_score,
+                     uint8_t *out_mapped, void *stream, const rawalign_opts *opts) {
+    if (n_reads < 0) return fail(RAWALIGN_EINVAL, "n_reads must be >= 0");
+    if (n_reads >= (int64_t)1 << 31) return fail(RAWALIGN_EINVAL, "n_reads must be < 2^31");
+    if (max_query < 0) return fail(RAWALIGN_EINVAL, "max_query must be >= 0");
+    if (block_rows < 64 || block_rows > ra::kEdgeCap)
+        return fail(RAWALIGN_EINVAL, "block_rows must be in [64, " + std::to_string(ra::kEdgeCap) + "]");
+    if (!std::isfinite(b_match) || std::isnan(threshold))
+        return fail(RAWALIGN_EINVAL, "b_match must be finite and threshold not NaN");
+    if (n_reads > 0 && (!cand_off || !cand_cnt || !n_events || !out_best || !out_best_score || !out_mapped))
+        return fail(RAWALIGN_EINVAL, "null pointer argument");
+    if (n_pairs > 0 && (!rows || !row_off)) return fail(RAWALIGN_EINVAL, "rows and row_off are required");
+    hipStream_t st = (hipStream_t)stream;
+    if (n_pairs > 0) {
+        int rc0 = check_call(Call{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+                                  nullptr, 0, nullptr, nullptr, st});
+        if (rc0) return rc0;
+    } else if (n_pairs < 0) {
+        return fail(RAWALIGN_EINVAL, "n_pairs must be >= 0");
+    }
+    rawalign_opts o = effective_opts(opts);
+    o.flags = 0;
+    int rc = check_opts(o);
+    if (rc) return rc;
+    if (n_pairs == 0 && n_reads == 0) return RAWALIGN_OK;
+    int dev = 0;
+    DeviceInfo info;
+    rc = device_info(dev, info);
+    if (rc) return rc;
+
+    ra::BnbScratch sc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        BnbStore &b = g_bnb[{dev, st}];
+        const int64_t np = std::max<int64_t>(n_pairs, 1), nr = std::max<int64_t>(n_reads, 1);
+        if (b.pairs < np || b.reads < nr) {
+            if (b.mem) (void)hipFree(b.mem);
+            b.mem = nullptr;
+            b.pairs = b.reads = 0;
+            const int64_t P = std::max(np, 2 * b.pairs), R = std::max(nr, 2 * b.reads);
+            // 8-byte fields first, then 4-byte, then 1-byte: every field stays aligned.
+            const size_t words = 2 * ra::kBuckets + 4;
+            const size_t bytes = (size_t)R * 8 + (size_t)P * 8 + words * 4 + (size_t)P + 256;
+            hipError_t e = hipMalloc(&b.mem, bytes);
+            if (e != hipSuccess) {
+                b.mem = nullptr;
+                return alloc_fail(e);
+            }
+            char *m = (char *)b.mem;
+            b.view.best = (uint64_t *)m;
+            m += (size_t)R * 8;
+            b.view.read_of = (int32_t *)m;
+            m += (size_t)P * 4;
+            b.view.list = (int32_t *)m;
+            m += (size_t)P * 4;
+            b.view.hist = (int32_t *)m;
+            b.view.counts = b.view.hist + 2 * ra::kBuckets;
+            b.view.queue = b.view.counts + 2;
+            m += words * 4;
+            b.view.status = (uint8_t *)m;
+            b.pairs = P;
+            b.reads = R;
+        }
+        sc = b.view;
+    }
+
+    ra::BnbArgs ba;
+    ba.a.q = q;
+    ba.a.q_size = q_size;
+    ba.a.q_off = q_off;
+    ba.a.q_len = q_len;
+    ba.a.r = r;
+    ba.a.r_size = r_size;
+    ba.a.r_off = r_off;
+    ba.a.r_len = r_len;
+    ba.a.out_score = out_score;
+    ba.a.out_end = out_end;
+    ba.a.rows = rows;
+    ba.a.rows_size = rows_size;
+    ba.a.row_off = row_off;
+    ba.a.first_chunk = nullptr;
+    ba.n_pairs = n_pairs;
+    ba.cand_off = cand_off;
+    ba.cand_cnt = cand_cnt;
+    ba.n_events = n_events;
+    ba.n_reads = n_reads;
+    ba.b_match = b_match;
+    ba.max_query = max_query;
+    ba.block_rows = block_rows;
+    ba.s = sc;
+
+    hipError_t e;
+    if (n_pairs > 0) {
+        // One persistent wave per resident slot, each with its own stripe edge slot.
+        const int grid = grid_of(info.cus, o.long_waves_per_cu, ra::bnb_blocks_per_cu());
+        StreamScratch *ss = nullptr;
+        rc = get_scratch(dev, st, n_pairs, grid, 0, false, false, ss);
+        if (rc) return rc;
+        if ((e = ra::launch_bnb(ba, grid, ss->edge, st)) != hipSuccess) return hip_fail(e, "early-termination kernels");
+    }
+    if (n_reads > 0) {
+        e = ra::launch_decide(out_score, n_pairs, cand_off, cand_cnt, n_events, n_reads, b_match, threshold, out_best,
+                              out_best_score, out_mapped, st);
+        if (e != hipSuccess) return hip_fail(e, "decide kernel");
+    }
+    return RAWALIGN_OK;
 }
 
 int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,

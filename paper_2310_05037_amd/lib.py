@@ -32,7 +32,7 @@ FLAG_TIMING = 1
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
     "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
-    "rawalign_decide", "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing",
+    "rawalign_decide", "rawalign_map_bnb", "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing",
     "rawalign_last_error", "rawalign_version",
 )
 
@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.rawalign_dtw_extend.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp,
                                       ctypes.POINTER(Opts)]
     L.rawalign_decide.argtypes = [vp, i64, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp]
+    L.rawalign_map_bnb.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp, i64, f64, f64, i32, i32,
+                                   vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_last_timing.argtypes = [ctypes.POINTER(Timing)]
@@ -166,6 +168,30 @@ def rawalign_dtw_extend(q, q_off, q_len, r, r_off, r_len, rows, row_off, first_c
                                       _dev(row_off, torch.int64, "row_off"),
                                       _dev(first_chunk, torch.uint8, "first_chunk"), n, a[9], a[10],
                                       _stream(stream), None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_map_bnb(q, q_off, q_len, r, r_off, r_len, cand_off, cand_cnt, n_events, rows, row_off,
+                     out_score, out_end, out_best, out_best_score, out_mapped, max_query, block_rows=512,
+                     b_match=0.4, threshold=20.0, opts=None, stream=None):
+    import torch
+    a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
+    n = a[8]
+    n_reads = cand_off.numel()
+    if row_off.numel() != n:
+        raise ValueError("row_off needs one entry per pair")
+    for t, nm in ((cand_cnt, "cand_cnt"), (n_events, "n_events"), (out_best, "out_best"),
+                  (out_best_score, "out_best_score"), (out_mapped, "out_mapped")):
+        if t.numel() != n_reads:
+            raise ValueError(f"{nm} has {t.numel()} elements, expected {n_reads}")
+    _check(load().rawalign_map_bnb(*a[:9], _dev(cand_off, torch.int64, "cand_off"),
+                                   _dev(cand_cnt, torch.int32, "cand_cnt"), _dev(n_events, torch.int32, "n_events"),
+                                   n_reads, float(b_match), float(threshold), int(max_query), int(block_rows),
+                                   _dev(rows, torch.float32, "rows"), rows.numel(),
+                                   _dev(row_off, torch.int64, "row_off"), a[9], a[10],
+                                   _dev(out_best, torch.int32, "out_best"),
+                                   _dev(out_best_score, torch.float64, "out_best_score"),
+                                   _dev(out_mapped, torch.uint8, "out_mapped"), _stream(stream),
+                                   None if opts is None else ctypes.byref(opts)))
 
 
 def rawalign_decide(score, cand_off, cand_cnt, n_events, out_best, out_score, out_mapped,

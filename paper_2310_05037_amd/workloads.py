@@ -235,6 +235,32 @@ def config4(n_pairs: int = 1024, n: int = 10_000, m: int = 20_000) -> Batch:
     return _pack("config4_long_stress", reads, pairs, r, {"config": 4, "reference_bases": len(bases)})
 
 
+def chain_ordered(b: Batch, seed: int = 0, p_true_first: float = 0.9) -> Batch:
+    """The same pairs with each read's candidates in a synthetic chaining-score
+    order (Sec. 2.4.1 visits candidates best chain first).  Chaining is not
+    modelled; its outcome is: with probability p_true_first the candidate
+    holding the read's source window comes first, otherwise it lands at a
+    uniform later position; decoys are in random order.  Reads keep their
+    contiguous candidate ranges."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 1000 + seed))
+    perm = np.arange(b.n_pairs, dtype=np.int64)
+    true_pair = b.true_pair.copy()
+    for k in range(len(b.cand_off)):
+        p0, cnt = int(b.cand_off[k]), int(b.cand_cnt[k])
+        if cnt <= 1:
+            continue
+        t = int(b.true_pair[k]) - p0
+        others = [c for c in range(cnt) if c != t]
+        rng.shuffle(others)
+        pos = 0 if rng.random() < p_true_first else int(rng.integers(1, cnt))
+        order = others[:pos] + [t] + others[pos:]
+        perm[p0:p0 + cnt] = p0 + np.array(order, dtype=np.int64)
+        true_pair[k] = p0 + pos
+    return Batch(b.name + "[chain_ordered]", b.q, b.r, b.q_off[perm], b.q_len[perm], b.r_off[perm], b.r_len[perm],
+                 b.cand_off.copy(), b.cand_cnt.copy(), b.n_events.copy(), true_pair,
+                 dict(b.meta, p_true_first=p_true_first))
+
+
 def random_pairs(rng, n_pairs, n_range, m_range, value_fn=None, share_query=False) -> Batch:
     """Unstructured pairs for edge-case tests: lengths uniform in the inclusive
     ranges, values from value_fn(rng, size) (default N(0, 1) float32)."""

@@ -79,6 +79,15 @@ def test_argument_errors_without_device(L):
     rc = so.rawalign_dtw_extend(fake, 10, fake, fake, fake, 10, fake, fake, None, 0, fake, fake, 2, fake, fake,
                                 None, None)
     assert rc == L.RAWALIGN_EINVAL
+    # early termination: bad block size, negative max_query, missing rows
+    def bnb(block_rows=512, max_query=100, rows=fake, n_reads=2):
+        return so.rawalign_map_bnb(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, fake, n_reads, 0.4,
+                                   20.0, max_query, block_rows, rows, 10, fake, fake, fake, fake, fake, fake, None,
+                                   None)
+    assert bnb(block_rows=32) == L.RAWALIGN_EINVAL and b"block_rows" in so.rawalign_last_error()
+    assert bnb(max_query=-1) == L.RAWALIGN_EINVAL and b"max_query" in so.rawalign_last_error()
+    assert bnb(rows=None) == L.RAWALIGN_EINVAL and b"rows" in so.rawalign_last_error()
+    assert bnb(n_reads=-1) == L.RAWALIGN_EINVAL and b"n_reads" in so.rawalign_last_error()
     # decide with a negative read count
     rc = so.rawalign_decide(fake, 1, fake, fake, fake, -1, 0.4, 20.0, fake, fake, fake, None)
     assert rc == L.RAWALIGN_EINVAL

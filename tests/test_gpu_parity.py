@@ -205,17 +205,24 @@ def test_config4_long_stress_sampled(L):
 
 
 def test_config2_persistent_vs_plain_and_sample(L):
-    """Full 100,000-pair uneven batch: persistent and plain bit-identical,
-    and a stratified sample of 200 pairs against the oracle."""
+    """Full 100,000-pair uneven batch: persistent (default and autotuned, the
+    setting the benchmark times) and plain bit-identical, and a stratified
+    sample of 200 pairs against the oracle."""
     b = W.config2()
     db = L.DeviceBatch(b)
     _say(f"  gpu: {b.name} persistent")
-    db.run()
+    db.run(opts=L.make_opts())
     s, e = db.results()
     _say(f"  gpu: {b.name} plain")
     db.run(plain=True)
     ps, pe = db.results()
     assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
+    _say(f"  gpu: {b.name} autotune")
+    best = L.rawalign_autotune(*db.args())
+    db.score.fill_(-1.0)
+    db.run(opts=best)
+    ts, te = db.results()
+    assert np.array_equal(s.view(np.uint32), ts.view(np.uint32)) and np.array_equal(e, te), best.as_dict()
     sample = parity.stratified_sample(b, 200)
     st = parity.check(b, s, e, pairs=sample)
     print("config2", st)
