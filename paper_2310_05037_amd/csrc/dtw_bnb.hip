@@ -190,6 +190,12 @@ RA_DEV void bnb_dispatch(int h, const PairView &pv, int S, float *edge, float &b
     }
 }
 
+// Wave priority (0..3) while sweeping a read's first candidate.
+#ifndef RA_BNB_FIRST_PRIO
+#define RA_BNB_FIRST_PRIO 0
+#endif
+constexpr int kBnbFirstPrio = RA_BNB_FIRST_PRIO;
+
 RA_DEV int bnb_next(int32_t *queue) {
     int it = 0;
     if (__lane_id() == 0) it = atomicAdd(queue, 1);
@@ -206,6 +212,14 @@ void k_bnb_run(BnbArgs b, float *edge_base) {
     int item = bnb_next(b.s.queue);
     while (item < n_items) {
         const int p = b.s.list[item];
+        // First candidates carry the longest dependency chains (their
+        // reads' bounds and, longest first, the kernel's critical path).
+        if (kBnbFirstPrio > 0) {
+            if (item < b.s.counts[0])
+                __builtin_amdgcn_s_setprio(kBnbFirstPrio);
+            else
+                __builtin_amdgcn_s_setprio(0);
+        }
         PairView pv;
         pv.q = a.q + a.q_off[p];
         pv.n = a.q_len[p];

@@ -12,15 +12,21 @@ constexpr int single_waves() {
     return KHI <= 8 ? 4 : (KHI <= 11 ? 3 : 2);
 }
 
+// Two chains per lane (see sweep) for the two-wave kernel of 34..64 columns
+// per lane, where fewer waves leave the SIMD fewer independent instructions.
+#ifndef RA_SINGLE_HI_ILP2
+#define RA_SINGLE_HI_ILP2 0
+#endif
+
 // Columns per lane C = 2H for H in [H, HMAX].
-template <bool EXT, int H, int HMAX>
+template <bool EXT, bool ILP2, int H, int HMAX>
 RA_DEV void single_dispatch(int h, const PairView &pv, float &best, int &bj) {
     if constexpr (H <= HMAX) {
         if (h == H) {
             float nc;
-            sweep<2 * H, EXT, false, false, false>(pv, 0, nullptr, 0.0f, nc, best, bj);
+            sweep<2 * H, EXT, false, false, ILP2>(pv, 0, nullptr, 0.0f, nc, best, bj);
         } else {
-            single_dispatch<EXT, H + 1, HMAX>(h, pv, best, bj);
+            single_dispatch<EXT, ILP2, H + 1, HMAX>(h, pv, best, bj);
         }
     }
 }
@@ -43,7 +49,7 @@ void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__r
         const int h = (pv.m + 127) >> 7;   // column pairs per lane
         float best = __builtin_nanf("");
         int bj = -2;
-        single_dispatch<EXT, 2 * KLO - 1, 2 * KHI>(h, pv, best, bj);
+        single_dispatch<EXT, (KLO > 8 && RA_SINGLE_HI_ILP2 != 0), 2 * KLO - 1, 2 * KHI>(h, pv, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

@@ -156,3 +156,21 @@ def test_latency_accounting_virtual_clock():
     drive(eng, clock)
     assert all(abs(x[2]) < 1e-12 for x in eng.latencies)
     assert eng.stats()["chunks"] == sum(len(st.results) for st in eng.reads)
+
+
+def test_chain_order_keeps_reads_and_places_true_region():
+    """The synthetic chaining order permutes candidates only within their
+    read, keeps every pair, and puts the true region first for about the
+    requested share of reads."""
+    b = W.config1(n_pairs=2000)
+    c = W.chain_ordered(b, seed=3, p_true_first=0.8)
+    assert np.array_equal(c.cand_off, b.cand_off) and np.array_equal(c.cand_cnt, b.cand_cnt)
+    for k in range(len(b.cand_off)):
+        p0, n = int(b.cand_off[k]), int(b.cand_cnt[k])
+        got = sorted(zip(c.r_off[p0:p0 + n].tolist(), c.q_off[p0:p0 + n].tolist(), c.r_len[p0:p0 + n].tolist()))
+        exp = sorted(zip(b.r_off[p0:p0 + n].tolist(), b.q_off[p0:p0 + n].tolist(), b.r_len[p0:p0 + n].tolist()))
+        assert got == exp
+        t = int(c.true_pair[k])
+        assert p0 <= t < p0 + n and c.r_off[t] == b.r_off[b.true_pair[k]]
+    share = float((c.true_pair == c.cand_off).mean())
+    assert 0.65 < share < 0.95
