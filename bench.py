@@ -87,11 +87,18 @@ KERNEL_SOURCES = ["dtw_device.h", "dtw_multi.hip", "internal.h"]
 
 
 def kernel_source_hash() -> str:
+    """sha256 of the sources that define the dominant kernel, with comments
+    and blank lines removed (so only code changes invalidate the counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2310_05037_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2310_05037_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = line.split("//", 1)[0].strip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -1,7 +1,8 @@
 // dtw_multi.hip -- regions longer than 4096 levels: one wave sweeps S column
-// stripes one after another.  Lane 63 writes each stripe's last column to
-// the wave's own edge slot in device memory; the next stripe's lane 0 reads
-// it back as its left neighbour.  Waves never wait for each other.
+// stripes of at most 256 kMultiMaxK columns (2048 by default) one after
+// another.  Lane 63 writes each stripe's last column to the wave's own edge
+// slot in device memory; the next stripe's lane 0 reads it back as its left
+// neighbour.  Waves never wait for each other.
 #include "dtw_device.h"
 
 namespace ra {

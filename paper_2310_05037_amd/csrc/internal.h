@@ -9,14 +9,14 @@
 namespace ra {
 
 // Routes a pair can take after planning:
-//   single_lo: one stripe, at most 32 columns per lane (region <= 2048 levels)
-//   single_hi: one stripe, 36..64 columns per lane (region <= 4096 levels)
-//   multi:     several 4096-column stripes swept one after another by the
-//              same wave (region > 4096 levels)
+//   single_lo: one stripe, 2..32 columns per lane (region <= 2048 levels)
+//   single_hi: one stripe, 34..64 columns per lane (region <= 4096 levels)
+//   multi:     several stripes of at most 256 kMultiMaxK columns swept one
+//              after another by the same wave (region > 4096 levels)
 enum Route : int { kRouteSingleLo = 0, kRouteSingleHi = 1, kRouteMulti = 2, kNumRoutes = 3 };
 
 constexpr int kMaxColsPerLane = 64;
-constexpr int kShortMaxRegion = 64 * kMaxColsPerLane;  // 4096: one stripe
+constexpr int kShortMaxRegion = 64 * kMaxColsPerLane;  // 4096: the widest single stripe
 constexpr int kSingleLoMaxRegion = 2048;               // 64 lanes x 32 columns
 constexpr int kMaxStripes = 16;
 constexpr int kMaxRegion = kMaxStripes * kShortMaxRegion;   // 65536

@@ -179,8 +179,8 @@ class Engine:
     # ---- scheduling ------------------------------------------------------------
     def _finish(self, st: ReadState, status: str):
         if st.admitted and st.row_off is not None:
-            for off, ln in zip(st.row_off, st.r_len):
-                self.arena.release(off, ln)
+            # one block per read: the candidates' rows are contiguous
+            self.arena.release(int(st.row_off[0]), int(st.r_len.astype(np.int64).sum()))
         st.row_off = None
         st.done = True
         st.status = status
@@ -201,16 +201,13 @@ class Engine:
         # arrival order: nobody overtakes a read that does not fit yet
         while self.pending:
             st = self.pending[0]
-            offs = []
+            lens = st.r_len.astype(np.int64)
             try:
-                for ln in st.r_len:
-                    offs.append(self.arena.alloc(ln))
+                base = self.arena.alloc(int(lens.sum()))   # one block for all the read's rows
             except ArenaFull:
-                for off, ln in zip(offs, st.r_len):
-                    self.arena.release(off, ln)
                 break
             self.pending.popleft()
-            st.row_off = np.array(offs, np.int64)
+            st.row_off = base + np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
             st.admitted = True
             st.status = "active"
             self._push(st)
