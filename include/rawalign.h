@@ -184,7 +184,9 @@ int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off
  *   - Read k's candidates cand_off[k] .. cand_off[k]+cand_cnt[k]-1 are taken
  *     to be in chaining-score order, best first.  Every read's first
  *     candidate is queued ahead of all other pairs (longest first within
- *     each group); one persistent kernel pulls pairs from that queue.
+ *     each group); one persistent kernel pulls pairs from that queue, and
+ *     waves sweeping a first candidate run at a raised wave priority (their
+ *     results bound the other pairs).
  *   - A pair is swept block_rows query rows at a time through its resident
  *     row rows[row_off[p] .. +r_len[p]) (scratch contents).  After a block
  *     that ended at row i the cost of every path is at least min_j D(i, j)

@@ -100,13 +100,16 @@ __global__ void k_bnb_prepare(BnbArgs b) {
 
 // Stripes of at most 2048 columns (C <= 32 columns per lane) for every
 // region; a region of m levels takes S = ceil(m / 2048)
-// stripes of 64 C columns, C = 2h, h the smallest with S * 128 h >= m.
+// stripes of 64 C columns, C = 2h, the smallest with S * 64 C >= m.
 constexpr int kBnbMaxK = 8;
+// Columns per lane in steps of 2: every count from 1 to 32 in one kernel
+// would more than quadruple its compile time.
+constexpr int kBnbColStep = 2;
 RA_DEV void bnb_shape(int m, int &S, int &h) {
     const int width = 256 * kBnbMaxK;
     S = (m + width - 1) / width;
     if (S < 1) S = 1;
-    h = (m + 128 * S - 1) / (128 * S);
+    h = (m + 64 * kBnbColStep * S - 1) / (64 * kBnbColStep * S);
 }
 
 // Group (0 first candidates, 1 others) and LPT bucket of pair p, or -1 when
@@ -117,7 +120,7 @@ RA_DEV int bnb_bin(const BnbArgs &b, int64_t p) {
     const int n = b.a.q_len[p];
     int S, h;
     bnb_shape(b.a.r_len[p], S, h);
-    const float work = (float)(n + 64) * (float)(S * 128 * h) + 1.0f;
+    const float work = (float)(n + 64) * (float)(S * 64 * kBnbColStep * h) + 1.0f;
     int k = (int)(4.0f * __log2f(work));
     k = k < 0 ? 0 : (k >= kBuckets ? kBuckets - 1 : k);
     return (st == kBnbFirst ? 0 : kBuckets) + (kBuckets - 1 - k);
@@ -182,9 +185,9 @@ __global__ __launch_bounds__(256) void k_bnb_scatter(BnbArgs b) {
 
 template <int H>
 RA_DEV void bnb_dispatch(int h, const PairView &pv, int S, float *edge, float &best, int &bj) {
-    if constexpr (H <= 2 * kBnbMaxK) {
+    if constexpr (H <= 4 * kBnbMaxK / kBnbColStep) {
         if (h == H)
-            multi_pair<2 * H, true>(pv, S, edge, best, bj);
+            multi_pair<kBnbColStep * H, true>(pv, S, edge, best, bj);
         else
             bnb_dispatch<H + 1>(h, pv, S, edge, best, bj);
     }
@@ -192,7 +195,7 @@ RA_DEV void bnb_dispatch(int h, const PairView &pv, int S, float *edge, float &b
 
 // Wave priority (0..3) while sweeping a read's first candidate.
 #ifndef RA_BNB_FIRST_PRIO
-#define RA_BNB_FIRST_PRIO 0
+#define RA_BNB_FIRST_PRIO 2
 #endif
 constexpr int kBnbFirstPrio = RA_BNB_FIRST_PRIO;
 

@@ -310,16 +310,20 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
     wave_min(best, bj);
 }
 
-// Stripe shape of a region of m levels: S stripes of 64*C columns, C = 2h
-// (h column pairs per lane).  Single-stripe pairs use the smallest h with
-// 128h >= m.  Multi-stripe pairs use S = ceil(m / (256 kMultiMaxK)) and the
-// smallest h with S * 128h >= m; then every stripe starts inside the region
-// ((S-1)*64*C < m over the whole range of m).
-RA_DEV void stripe_shape(int m, int &S, int &h) {
-    const int width = m <= kSingleMaxRegion ? kSingleMaxRegion : 256 * kMultiMaxK;
+// Stripe shape of a region of m levels: S stripes of 64*C columns,
+// C = step h (step: kSingleColStep or kMultiColStep).  Single-stripe pairs
+// use the smallest h with 64 C >= m.  Multi-stripe pairs use
+// S = ceil(m / (256 kMultiMaxK)) and the smallest h with S * 64 C >= m; then
+// every stripe starts inside the region ((S-1)*64*C < m over the whole
+// range of m).  Returns the padded columns of one stripe, 64 C.
+RA_DEV int stripe_shape(int m, int &S, int &h) {
+    const bool single = m <= kSingleMaxRegion;
+    const int width = single ? kSingleMaxRegion : 256 * kMultiMaxK;
+    const int group = 64 * (single ? kSingleColStep : kMultiColStep);
     S = (m + width - 1) / width;
     if (S < 1) S = 1;
-    h = (m + 128 * S - 1) / (128 * S);
+    h = (m + group * S - 1) / (group * S);
+    return group * h;
 }
 
 // Two independent min-plus chains per lane (the lane's two column halves one
@@ -330,6 +334,7 @@ RA_DEV void stripe_shape(int m, int &S, int &h) {
 #define RA_MULTI_ILP2 0
 #endif
 constexpr bool kMultiIlp2 = RA_MULTI_ILP2 != 0;
+static_assert(!kMultiIlp2 || kMultiColStep == 2, "the two-chain sweep needs an even column count");
 
 // One pair swept stripe by stripe by one wave (several stripes when the
 // region is wider than one): lane 63 stores each stripe's last column into

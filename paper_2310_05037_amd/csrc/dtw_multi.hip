@@ -17,24 +17,24 @@ constexpr int kMultiWaves = kMultiMaxK <= 8 ? 4 : (kMultiMaxK <= 12 ? 3 : 2);
 // Narrowest stripe any region above one stripe gets from stripe_shape: the
 // smallest h = ceil(m / (128 S)) over m in (kSingleMaxRegion, kMaxRegion].
 constexpr int multi_min_h() {
-    int hmin = 2 * kMultiMaxK;
+    int hmin = 4 * kMultiMaxK / kMultiColStep;
     for (int m = kSingleMaxRegion + 1; m <= kMaxRegion; ++m) {
         const int w = 256 * kMultiMaxK;
         const int S = (m + w - 1) / w;
-        const int h = (m + 128 * S - 1) / (128 * S);
+        const int h = (m + 64 * kMultiColStep * S - 1) / (64 * kMultiColStep * S);
         if (h < hmin) hmin = h;
     }
     return hmin;
 }
 constexpr int kMultiMinH = multi_min_h();
-constexpr int kMultiMaxH = 2 * kMultiMaxK;
+constexpr int kMultiMaxH = 4 * kMultiMaxK / kMultiColStep;
 
 // Columns per lane C = 2H for every H in [kMultiMinH, kMultiMaxH].
 template <int H, bool EXT>
 RA_DEV void multi_dispatch(int h, const PairView &pv, int S, float *edge, float &best, int &bj) {
     if constexpr (H <= kMultiMaxH) {
         if (h == H)
-            multi_pair<2 * H, EXT>(pv, S, edge, best, bj);
+            multi_pair<kMultiColStep * H, EXT>(pv, S, edge, best, bj);
         else
             multi_dispatch<H + 1, EXT>(h, pv, S, edge, best, bj);
     }

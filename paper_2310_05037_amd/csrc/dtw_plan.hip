@@ -54,8 +54,8 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
         // cells (n + 64 steps per stripe x the stripe's padded columns),
         // bucket 0 holding the largest pairs.
         int S, h;
-        stripe_shape(m, S, h);
-        const float work = (float)(n + 64) * (float)(S * 128 * h) + 1.0f;
+        const int cols = stripe_shape(m, S, h);
+        const float work = (float)(n + 64) * (float)(S * cols) + 1.0f;
         int b = (int)(4.0f * __log2f(work));
         b = b < 0 ? 0 : (b >= pa.buckets ? pa.buckets - 1 : b);
         bucket = pa.buckets - 1 - b;

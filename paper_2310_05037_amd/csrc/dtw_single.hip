@@ -24,7 +24,7 @@ RA_DEV void single_dispatch(int h, const PairView &pv, float &best, int &bj) {
     if constexpr (H <= HMAX) {
         if (h == H) {
             float nc;
-            sweep<2 * H, EXT, false, false, ILP2>(pv, 0, nullptr, 0.0f, nc, best, bj);
+            sweep<kSingleColStep * H, EXT, false, false, ILP2>(pv, 0, nullptr, 0.0f, nc, best, bj);
         } else {
             single_dispatch<EXT, ILP2, H + 1, HMAX>(h, pv, best, bj);
         }
@@ -46,10 +46,11 @@ void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__r
     while (item < n_items) {
         const int p = list[item];
         const PairView pv = pair_view<EXT>(a, p);
-        const int h = (pv.m + 127) >> 7;   // column pairs per lane
+        const int h = (pv.m + 64 * kSingleColStep - 1) / (64 * kSingleColStep);   // C = 2h columns per lane
         float best = __builtin_nanf("");
         int bj = -2;
-        single_dispatch<EXT, (KLO > 8 && RA_SINGLE_HI_ILP2 != 0), 2 * KLO - 1, 2 * KHI>(h, pv, best, bj);
+        single_dispatch<EXT, (KLO > 8 && RA_SINGLE_HI_ILP2 != 0), 4 * (KLO - 1) / kSingleColStep + 1,
+                        4 * KHI / kSingleColStep>(h, pv, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

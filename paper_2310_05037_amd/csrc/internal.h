@@ -20,6 +20,17 @@ constexpr int kShortMaxRegion = 64 * kMaxColsPerLane;  // 4096: the widest singl
 constexpr int kSingleLoMaxRegion = 2048;               // 64 lanes x 32 columns
 constexpr int kMaxStripes = 16;
 constexpr int kMaxRegion = kMaxStripes * kShortMaxRegion;   // 65536
+// Columns per lane come in steps (C = step * h).  Single-stripe kernels use
+// steps of 2 (32 column counts per kernel).  The multi-stripe and
+// early-termination kernels use steps of 1 by default, which halves the
+// padding columns past the end of a region; the two-chain sweep needs 2.
+constexpr int kSingleColStep = 2;
+#ifndef RA_MULTI_COL_STEP
+#define RA_MULTI_COL_STEP 1
+#endif
+constexpr int kMultiColStep = RA_MULTI_COL_STEP;
+static_assert(kMultiColStep == 1 || kMultiColStep == 2, "column step");
+
 // Widest region the single-stripe kernel takes, in groups of 4 columns per
 // lane (16: 4096 levels at two waves per SIMD; 11: 2816 levels at three).
 #ifndef RA_SINGLE_HI_KMAX
