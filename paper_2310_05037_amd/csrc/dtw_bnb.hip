@@ -195,7 +195,7 @@ RA_DEV void bnb_dispatch(int h, const PairView &pv, int S, float *edge, float &b
 
 // Wave priority (0..3) while sweeping a read's first candidate.
 #ifndef RA_BNB_FIRST_PRIO
-#define RA_BNB_FIRST_PRIO 2
+#define RA_BNB_FIRST_PRIO 0
 #endif
 constexpr int kBnbFirstPrio = RA_BNB_FIRST_PRIO;
 
@@ -207,7 +207,10 @@ RA_DEV int bnb_next(int32_t *queue) {
 
 // Three waves per SIMD: at four, every column count from 2 to 32 in one
 // kernel plus the block loop spill registers.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
+#ifndef RA_BNB_WAVES
+#define RA_BNB_WAVES 3
+#endif
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RA_BNB_WAVES, RA_BNB_WAVES)))
 void k_bnb_run(BnbArgs b, float *edge_base) {
     float *edge = edge_base + (size_t)blockIdx.x * kEdgeCap;
     const PairArrays &a = b.a;
