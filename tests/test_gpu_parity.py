@@ -283,3 +283,43 @@ def test_autotune_and_tuning_cache(L, tmp_path):
     db.run()   # opts NULL: the tuned setting
     s1, e1 = db.results()
     assert np.array_equal(s0.view(np.uint32), s1.view(np.uint32)) and np.array_equal(e0, e1)
+
+
+def test_million_event_query_and_64bit_offsets(L):
+    """A single-stripe pair with a query of a million events, and pairs whose
+    query and region slices start beyond 2^31 elements (8 GiB arrays), against
+    the float oracle bit for bit."""
+    import torch
+    from oracle import oracle
+    rng = np.random.default_rng(11)
+    dev = "cuda"
+    big = (1 << 31) + 4096
+    q_long = rng.standard_normal(1_000_003).astype(np.float32)
+    r_small = rng.standard_normal(100).astype(np.float32)
+    q_hi = rng.standard_normal(300).astype(np.float32)
+    r_hi = rng.standard_normal(5000).astype(np.float32)
+    _say("  gpu: 8 GiB query and region arrays for 64-bit offsets")
+    q = torch.zeros(big, dtype=torch.float32, device=dev)
+    r = torch.zeros(big, dtype=torch.float32, device=dev)
+    q[:len(q_long)] = torch.from_numpy(q_long).to(dev)
+    r[:len(r_small)] = torch.from_numpy(r_small).to(dev)
+    qo, ro = (1 << 31) + 7, (1 << 31) - 1000   # the region straddles 2^31
+    q[qo:qo + len(q_hi)] = torch.from_numpy(q_hi).to(dev)
+    r[ro:ro + len(r_hi)] = torch.from_numpy(r_hi).to(dev)
+    rows = [(0, len(q_long), 0, len(r_small)), (qo, len(q_hi), ro, len(r_hi)), (qo, len(q_hi), ro, 1500)]
+    t = lambda xs, dt: torch.tensor(xs, dtype=dt, device=dev)
+    q_off = t([x[0] for x in rows], torch.int64)
+    q_len = t([x[1] for x in rows], torch.int32)
+    r_off = t([x[2] for x in rows], torch.int64)
+    r_len = t([x[3] for x in rows], torch.int32)
+    sc = torch.empty(len(rows), dtype=torch.float32, device=dev)
+    en = torch.empty(len(rows), dtype=torch.int32, device=dev)
+    L.rawalign_dtw_batch_ex(q, q_off, q_len, r, r_off, r_len, sc, en)
+    torch.cuda.synchronize()
+    s, e = sc.cpu().numpy(), en.cpu().numpy()
+    del q, r
+    torch.cuda.empty_cache()
+    refs = [(q_long, r_small), (q_hi, r_hi), (q_hi, r_hi[:1500])]
+    for i, (qq, rr) in enumerate(refs):
+        c32, e32 = oracle.dtw_f32(qq, rr)
+        assert s[i].view(np.uint32) == np.float32(c32).view(np.uint32) and e[i] == e32, i
