@@ -17,7 +17,7 @@
 #include "internal.h"
 #include "rawalign.h"
 
-#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.2.0"
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.3.0"
 
 namespace {
 

@@ -149,6 +149,10 @@ class Engine:
         self.rejected = 0
         self.peak_arena = 0
         self.failed_ticks = 0
+        # Backends with launch/poll run up to `slots` ticks at once.
+        self.async_backend = hasattr(backend, "launch") and getattr(backend, "slots", 1) > 1
+        self.slots = getattr(backend, "slots", 1) if self.async_backend else 1
+        self.inflight = collections.deque()   # (token, TickBatch) launched, results pending
 
     # ---- submission ------------------------------------------------------------
     def submit(self, rid: int, arrival: float, events: np.ndarray, r_off, r_len):
@@ -242,23 +246,15 @@ class Engine:
                          np.concatenate(first), np.concatenate([[0], np.cumsum(cc)[:-1]]).astype(np.int64), cc,
                          np.array(n_ev, np.int32))
 
-    def tick(self) -> int:
-        """One scheduling step; returns the number of chunks processed."""
-        now = self.clock()
-        self._admit(now)
-        ready = self._ready(now)
-        if not ready:
-            return 0
-        b = self._batch(ready)
-        try:
-            score, end, best, best_score, mapped = self.backend.run(b, self.b_match, self.threshold)
-        except Exception:
-            # fail only the reads of this tick; the rest continue
-            self.failed_ticks += 1
-            for st in b.reads:
+    def _fail(self, b: TickBatch):
+        """A backend error fails only the reads of that tick."""
+        self.failed_ticks += 1
+        for st in b.reads:
+            if not st.done:
                 self._finish(st, "failed")
-            return 0
-        t_done = self.clock()
+
+    def _complete(self, b: TickBatch, results, t_done: float) -> int:
+        score, end, best, best_score, mapped = results
         self.ticks += 1
         self.jobs += b.n_jobs
         self.cells += b.cells
@@ -279,6 +275,47 @@ class Engine:
                 self._push(st)
         return len(b.reads)
 
+    def tick(self) -> int:
+        """One scheduling step: collect the ticks that finished, then start
+        one with every chunk available now (if a slot is free).  Returns the
+        number of chunks completed or started."""
+        done = 0
+        if self.inflight:
+            still = collections.deque()
+            for token, b in self.inflight:
+                try:
+                    res = self.backend.poll(token)
+                except Exception:
+                    self._fail(b)
+                    continue
+                if res is None:
+                    still.append((token, b))
+                else:
+                    done += self._complete(b, res, self.clock())
+            self.inflight = still
+        now = self.clock()
+        self._admit(now)
+        if len(self.inflight) >= self.slots:
+            return done
+        ready = self._ready(now)
+        if not ready:
+            return done
+        b = self._batch(ready)
+        if self.async_backend:
+            try:
+                token = self.backend.launch(b, self.b_match, self.threshold)
+            except Exception:
+                self._fail(b)
+                return done
+            self.inflight.append((token, b))
+            return done + len(b.reads)
+        try:
+            res = self.backend.run(b, self.b_match, self.threshold)
+        except Exception:
+            self._fail(b)
+            return done
+        return done + self._complete(b, res, self.clock())
+
     def all_done(self) -> bool:
         return self.n_done == len(self.reads)
 
@@ -290,12 +327,15 @@ class Engine:
             t.append(self.future[self.next_future].arrival)
         return min(t) if t else None
 
-    def run(self, idle_sleep: float = 2e-4, timeout: float | None = None):
+    def run(self, idle_sleep: float = 2e-4, poll_sleep: float = 2e-5, timeout: float | None = None):
         t0 = self.clock()
-        while not self.all_done():
+        while not self.all_done() or self.inflight:
             if self.tick() == 0:
                 if timeout is not None and self.clock() - t0 > timeout:
                     raise TimeoutError("serving loop did not finish")
+                if self.inflight:
+                    time.sleep(poll_sleep)
+                    continue
                 nxt = self.next_event_time()
                 if nxt is None and self.pending:
                     raise RuntimeError("reads wait for arena room that no running read will free")
@@ -314,26 +354,12 @@ class Engine:
                 "peak_arena_bytes": int(self.peak_arena) * 4, "arena_bytes": self.arena.size * 4}
 
 
-class GpuBackend:
-    """librawalign on one device: rawalign_dtw_extend over the tick's jobs,
-    then rawalign_decide over its reads.  With use_graph, the tick (pinned
-    host-to-device copies, both library calls, device-to-host copies) is
-    captured once into a HIP graph over fixed-capacity tables and replayed;
-    unused job slots carry q_len = -1 (sentinel, no kernel work) and unused
-    read slots no candidates."""
+class _Slot:
+    """Pinned host tables, device tables, outputs, stream and graph of one
+    tick in flight."""
 
-    def __init__(self, r_levels: np.ndarray, arena_floats: int, chunk: int = 400, max_jobs: int = 1 << 15,
-                 max_reads: int = 4096, use_graph: bool = True, opts=None):
-        import torch
-        from . import lib
-        self.torch, self.lib = torch, lib
-        dev = torch.device("cuda", torch.cuda.current_device())
-        self.chunk, self.max_jobs, self.max_reads = chunk, max_jobs, max_reads
-        self.r = torch.from_numpy(np.ascontiguousarray(r_levels, np.float32)).to(dev)
-        self.rows = torch.zeros(int(arena_floats), dtype=torch.float32, device=dev)
-        self.opts = opts
+    def __init__(self, torch, dev, chunk, J, R):
         pin = dict(pin_memory=True)
-        J, R = max_jobs, max_reads
         self.h = {"q": torch.zeros(R * chunk, dtype=torch.float32, **pin),
                   "q_off": torch.zeros(J, dtype=torch.int64, **pin), "q_len": torch.zeros(J, dtype=torch.int32, **pin),
                   "r_off": torch.zeros(J, dtype=torch.int64, **pin), "r_len": torch.zeros(J, dtype=torch.int32, **pin),
@@ -348,23 +374,52 @@ class GpuBackend:
                       "mapped": torch.empty(R, dtype=torch.uint8, device=dev)}
         self.h_out = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in self.d_out.items()}
         self.stream = torch.cuda.Stream()
-        self.use_graph = use_graph
+        self.event = torch.cuda.Event()
         self.graph = None
+        self.busy = False
+        self.shape = (0, 0)   # jobs and reads of the tick in flight
+
+
+class GpuBackend:
+    """librawalign on one device: rawalign_dtw_extend over the tick's jobs,
+    then rawalign_decide over its reads.  With use_graph, a tick (pinned
+    host-to-device copies, both library calls, device-to-host copies) is
+    captured once into a HIP graph over fixed-capacity tables and replayed;
+    unused job slots carry q_len = -1 (sentinel, no kernel work) and unused
+    read slots no candidates.  With slots > 1, up to that many ticks are in
+    flight at once, each with its own tables, stream and graph (launch/poll):
+    a chunk that becomes available while a tick runs does not wait for it.
+    Ticks in flight never share a read (a read's next chunk is scheduled only
+    after its results are back), so their rows are disjoint."""
+
+    def __init__(self, r_levels: np.ndarray, arena_floats: int, chunk: int = 400, max_jobs: int = 1 << 15,
+                 max_reads: int = 4096, use_graph: bool = True, opts=None, slots: int = 2):
+        import torch
+        from . import lib
+        self.torch, self.lib = torch, lib
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.chunk, self.max_jobs, self.max_reads = chunk, max_jobs, max_reads
+        self.r = torch.from_numpy(np.ascontiguousarray(r_levels, np.float32)).to(dev)
+        self.rows = torch.zeros(int(arena_floats), dtype=torch.float32, device=dev)
+        self.opts = opts
+        self.use_graph = use_graph
+        self.slots = int(slots)
+        self.slot = [_Slot(torch, dev, chunk, max_jobs, max_reads) for _ in range(self.slots)]
         self.params = None
 
-    def _work(self, b_match, threshold):
-        d, o = self.d, self.d_out
-        for k in self.h:
-            d[k].copy_(self.h[k], non_blocking=True)
+    def _work(self, sl: _Slot, b_match, threshold):
+        d, o = sl.d, sl.d_out
+        for k in sl.h:
+            d[k].copy_(sl.h[k], non_blocking=True)
         self.lib.rawalign_dtw_extend(d["q"], d["q_off"], d["q_len"], self.r, d["r_off"], d["r_len"], self.rows,
                                      d["row_off"], d["first"], o["score"], o["end"], opts=self.opts)
         self.lib.rawalign_decide(o["score"], d["cand_off"], d["cand_cnt"], d["n_events"], o["best"],
                                  o["best_score"], o["mapped"], b_match=b_match, threshold=threshold)
         for k in o:
-            self.h_out[k].copy_(o[k], non_blocking=True)
+            sl.h_out[k].copy_(o[k], non_blocking=True)
 
-    def _fill(self, b: TickBatch):
-        h = self.h
+    def _fill(self, sl: _Slot, b: TickBatch):
+        h = sl.h
         nj, nr = b.n_jobs, len(b.reads)
         if nj > self.max_jobs or nr > self.max_reads:
             raise ValueError("tick larger than the backend tables")
@@ -388,54 +443,75 @@ class GpuBackend:
         cc[nr:] = 0
         h["n_events"].numpy()[:nr] = b.n_events
 
-    def _blank(self):
-        self.h["q_len"].fill_(-1)
-        self.h["cand_cnt"].fill_(0)
-
     def prepare(self, b_match: float, threshold: float):
-        """Warm up over blank tables (every slot a sentinel, the rows
-        untouched) so the library allocates its scratch outside any capture,
-        then capture one tick into a graph.  The graph reads the pinned host
-        tables when it is replayed, so it serves every later tick."""
+        """Per slot: warm up over blank tables (every slot a sentinel, the
+        rows untouched) so the library allocates its scratch outside any
+        capture, then capture one tick into a graph and replay it once (the
+        first replay uploads it).  The graph reads the pinned host tables
+        when it is replayed, so it serves every later tick of that slot."""
         torch = self.torch
-        self._blank()
-        with torch.cuda.stream(self.stream):
-            self._work(b_match, threshold)
-            self.stream.synchronize()
-            if self.use_graph:
-                g = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(g, stream=self.stream):
-                    self._work(b_match, threshold)
-                self.graph = g
-                g.replay()                  # the first replay uploads the graph
-                self.stream.synchronize()
+        for sl in self.slot:
+            sl.h["q_len"].fill_(-1)
+            sl.h["cand_cnt"].fill_(0)
+            with torch.cuda.stream(sl.stream):
+                self._work(sl, b_match, threshold)
+                sl.stream.synchronize()
+                if self.use_graph:
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=sl.stream):
+                        self._work(sl, b_match, threshold)
+                    sl.graph = g
+                    g.replay()
+                    sl.stream.synchronize()
         self.params = (b_match, threshold)
 
-    def run(self, b: TickBatch, b_match: float, threshold: float):
-        torch = self.torch
+    def launch(self, b: TickBatch, b_match: float, threshold: float) -> int:
         if self.params != (b_match, threshold):
+            if any(sl.busy for sl in self.slot):
+                raise RuntimeError("decision parameters changed while ticks are in flight")
             self.prepare(b_match, threshold)
-        self._fill(b)
-        with torch.cuda.stream(self.stream):
+        i = next((k for k, sl in enumerate(self.slot) if not sl.busy), None)
+        if i is None:
+            raise RuntimeError("no free tick slot")
+        sl = self.slot[i]
+        self._fill(sl, b)
+        with self.torch.cuda.stream(sl.stream):
             if self.use_graph:
-                self.graph.replay()
+                sl.graph.replay()
             else:
-                self._work(b_match, threshold)
-        self.stream.synchronize()
-        nj, nr = b.n_jobs, len(b.reads)
-        o = self.h_out
+                self._work(sl, b_match, threshold)
+            sl.event.record(sl.stream)
+        sl.busy = True
+        sl.shape = (b.n_jobs, len(b.reads))
+        return i
+
+    def poll(self, i: int):
+        """Results of the tick in slot i, or None while it runs."""
+        sl = self.slot[i]
+        if not sl.event.query():
+            return None
+        sl.busy = False
+        nj, nr = sl.shape
+        o = sl.h_out
         return (o["score"].numpy()[:nj].copy(), o["end"].numpy()[:nj].copy(), o["best"].numpy()[:nr].copy(),
                 o["best_score"].numpy()[:nr].copy(), o["mapped"].numpy()[:nr].copy())
 
+    def run(self, b: TickBatch, b_match: float, threshold: float):
+        """Synchronous tick (one slot at a time)."""
+        i = self.launch(b, b_match, threshold)
+        self.slot[i].event.synchronize()
+        return self.poll(i)
+
 
 def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
-          max_jobs: int = 1 << 15, max_reads: int = 4096, timeout: float | None = None, backend=None):
+          max_jobs: int = 1 << 15, max_reads: int = 4096, timeout: float | None = None, backend=None,
+          slots: int = 2):
     """Run a workloads.ServingWorkload through the engine on the GPU.
     time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
-    period becomes 10 ms)."""
+    period becomes 10 ms); slots is the number of ticks in flight."""
     arena_floats = arena_bytes // 4
     if backend is None:
-        backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph)
+        backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph, slots=slots)
     # The engine's clock starts at zero when the loop starts, after every read
     # has been submitted (submitting many reads takes a while itself).
     origin = [time.perf_counter()]

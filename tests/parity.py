@@ -14,7 +14,6 @@ Sentinels (empty query / region, invalid slice) are compared exactly.
 """
 from __future__ import annotations
 
-import math
 import os
 
 import numpy as np

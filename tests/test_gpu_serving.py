@@ -129,17 +129,18 @@ def _oracle_engine(wl):
     return eng
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_serving_loop_matches_oracle_engine(L, use_graph):
+@pytest.mark.parametrize("use_graph,slots", [(True, 2), (False, 2), (True, 1)])
+def test_serving_loop_matches_oracle_engine(L, use_graph, slots):
     """The serving loop on the GPU (real clock, time-compressed arrivals,
-    graph-replayed or eager ticks) returns for every read and chunk exactly
-    what the oracle-backed engine returns, whatever the tick batching."""
+    graph-replayed or eager ticks, one or two ticks in flight) returns for
+    every read and chunk exactly what the oracle-backed engine returns,
+    whatever the tick batching."""
     from paper_2310_05037_amd import serve
     wl = W.serving_workload(60, rate=200.0, chunk=400, max_chunks=4, max_cands=8, ref_bases=200_000,
                             period=1.0, seed_index=33)
-    _say(f"  gpu: serving reads={len(wl.reads)} graph={use_graph}")
+    _say(f"  gpu: serving reads={len(wl.reads)} graph={use_graph} slots={slots}")
     eng, st = serve.serve(wl, arena_bytes=64 << 20, time_scale=0.02, use_graph=use_graph, max_jobs=1024,
-                          max_reads=128, timeout=120)
+                          max_reads=128, timeout=120, slots=slots)
     print("serving", st)
     ref = _oracle_engine(wl)
     assert st["failed"] == 0 and st["ticks"] > 0

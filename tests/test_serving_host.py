@@ -21,9 +21,13 @@ class VClock:
 def drive(eng, clock, dt=None, max_ticks=100000):
     """Advance the virtual clock to the next event (or by dt) and tick."""
     for _ in range(max_ticks):
-        if eng.all_done():
+        if eng.all_done() and not eng.inflight:
             return
         if eng.tick() == 0:
+            if eng.inflight:          # waiting for launched ticks: keep polling
+                if dt:
+                    clock.t += dt
+                continue
             nxt = eng.next_event_time()
             if nxt is None:
                 raise RuntimeError("stuck")
@@ -174,3 +178,55 @@ def test_chain_order_keeps_reads_and_places_true_region():
         assert p0 <= t < p0 + n and c.r_off[t] == b.r_off[b.true_pair[k]]
     share = float((c.true_pair == c.cand_off).mean())
     assert 0.65 < share < 0.95
+
+
+class AsyncOracle(OracleBackend):
+    """Oracle backend with launch/poll: a tick's results appear only after a
+    few polls, so several ticks are in flight at once."""
+    slots = 2
+
+    def __init__(self, *a, delay=3, **k):
+        super().__init__(*a, **k)
+        self.delay = delay
+        self.pending = {}
+        self.next_token = 0
+        self.max_inflight = 0
+
+    def launch(self, b, b_match, threshold):
+        res = self.run(b, b_match, threshold)
+        tok = self.next_token
+        self.next_token += 1
+        self.pending[tok] = [self.delay, res]
+        self.max_inflight = max(self.max_inflight, len(self.pending))
+        return tok
+
+    def poll(self, tok):
+        entry = self.pending[tok]
+        if entry[0] > 0:
+            entry[0] -= 1
+            return None
+        del self.pending[tok]
+        return entry[1]
+
+
+def test_ticks_in_flight_give_the_same_results():
+    """With two ticks in flight (launch/poll) every read gets the same
+    per-chunk results and status as with synchronous ticks, and no more than
+    two ticks are ever in flight."""
+    wl = small_workload(n_reads=16, seed_index=5)
+    runs = []
+    for be in (OracleBackend(wl.r, 1 << 20), AsyncOracle(wl.r, 1 << 20)):
+        clock = VClock()
+        eng = serve.Engine(be, 1 << 20, wl.chunk, wl.period, clock=clock)
+        assert eng.slots == (2 if isinstance(be, AsyncOracle) else 1)
+        for i, rd in enumerate(wl.reads):
+            eng.submit(i, rd.arrival, rd.events, rd.r_off, rd.r_len)
+        drive(eng, clock, dt=wl.period / 7)
+        assert not eng.inflight
+        runs.append((eng, be))
+    (e1, _), (e2, be2) = runs
+    assert be2.max_inflight == 2
+    for a, b in zip(e1.reads, e2.reads):
+        assert a.status == b.status and len(a.results) == len(b.results)
+        for x, y in zip(a.results, b.results):
+            assert x[:3] == y[:3] and np.array_equal(x[3], y[3]) and np.array_equal(x[4], y[4])
