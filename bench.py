@@ -142,8 +142,8 @@ def serving_leg(n_reads: int, rate: float):
     wl = workloads.serving_workload(n_reads, rate=rate)
     _, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600)
     keep = ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "reads", "ticks", "jobs", "mapped", "unmapped",
-            "failed", "peak_arena_bytes", "wall_s", "gcups", "chunks_per_s", "worst_ms")
-    out = {k: st[k] for k in keep}
+            "failed", "peak_arena_bytes", "wall_s", "gcups", "chunks_per_s", "worst_ms", "tick_device_ms")
+    out = {k: st[k] for k in keep if k in st}
     out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period,
                 "latency": "decision on host minus the moment the chunk was available"})
     return out

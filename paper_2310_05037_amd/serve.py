@@ -374,7 +374,8 @@ class _Slot:
                       "mapped": torch.empty(R, dtype=torch.uint8, device=dev)}
         self.h_out = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in self.d_out.items()}
         self.stream = torch.cuda.Stream()
-        self.event = torch.cuda.Event()
+        self.start = torch.cuda.Event(enable_timing=True)
+        self.event = torch.cuda.Event(enable_timing=True)
         self.graph = None
         self.busy = False
         self.shape = (0, 0)   # jobs and reads of the tick in flight
@@ -406,6 +407,7 @@ class GpuBackend:
         self.slots = int(slots)
         self.slot = [_Slot(torch, dev, chunk, max_jobs, max_reads) for _ in range(self.slots)]
         self.params = None
+        self.tick_ms = []   # device time of every tick (first copy to last copy)
 
     def _work(self, sl: _Slot, b_match, threshold):
         d, o = sl.d, sl.d_out
@@ -476,6 +478,7 @@ class GpuBackend:
         sl = self.slot[i]
         self._fill(sl, b)
         with self.torch.cuda.stream(sl.stream):
+            sl.start.record(sl.stream)
             if self.use_graph:
                 sl.graph.replay()
             else:
@@ -491,6 +494,7 @@ class GpuBackend:
         if not sl.event.query():
             return None
         sl.busy = False
+        self.tick_ms.append(sl.start.elapsed_time(sl.event))
         nj, nr = sl.shape
         o = sl.h_out
         return (o["score"].numpy()[:nj].copy(), o["end"].numpy()[:nj].copy(), o["best"].numpy()[:nr].copy(),
@@ -504,11 +508,13 @@ class GpuBackend:
 
 
 def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
-          max_jobs: int = 1 << 15, max_reads: int = 4096, timeout: float | None = None, backend=None,
+          max_jobs: int = 8192, max_reads: int = 256, timeout: float | None = None, backend=None,
           slots: int = 2):
     """Run a workloads.ServingWorkload through the engine on the GPU.
     time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
-    period becomes 10 ms); slots is the number of ticks in flight."""
+    period becomes 10 ms); slots is the number of ticks in flight.
+    max_jobs/max_reads size the per-tick tables (a captured tick copies them
+    whole); chunks beyond them wait for the next tick."""
     arena_floats = arena_bytes // 4
     if backend is None:
         backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph, slots=slots)
@@ -536,4 +542,8 @@ def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_gra
                       for rid, c, lat in worst]
     st.update({"wall_s": wall, "gcups": eng.cells / wall / 1e9, "chunks_per_s": st["chunks"] / wall,
                "time_scale": time_scale, "rate_reads_per_s": workload.rate / time_scale})
+    tick_ms = getattr(backend, "tick_ms", None)
+    if tick_ms:
+        st["tick_device_ms"] = {"p50": float(np.percentile(tick_ms, 50)), "p99": float(np.percentile(tick_ms, 99)),
+                                "max": float(np.max(tick_ms))}
     return eng, st
