@@ -355,24 +355,36 @@ class Engine:
 
 
 class _Slot:
-    """Pinned host tables, device tables, outputs, stream and graph of one
-    tick in flight."""
+    """Tables, outputs, stream and graph of one tick in flight.  The input
+    tables live in one pinned host buffer and one device buffer of the same
+    layout (one copy per direction per tick), likewise the outputs."""
+
+    IN = (("q", "float32", "R*chunk"), ("q_off", "int64", "J"), ("r_off", "int64", "J"), ("row_off", "int64", "J"),
+          ("cand_off", "int64", "R"), ("q_len", "int32", "J"), ("r_len", "int32", "J"), ("cand_cnt", "int32", "R"),
+          ("n_events", "int32", "R"), ("first", "uint8", "J"))
+    OUT = (("best_score", "float64", "R"), ("score", "float32", "J"), ("end", "int32", "J"), ("best", "int32", "R"),
+           ("mapped", "uint8", "R"))
+
+    @staticmethod
+    def _views(torch, fields, sizes, device, pin):
+        """One byte buffer split into 256-byte aligned typed views."""
+        spans, off = [], 0
+        for name, dt, n in fields:
+            dtype = getattr(torch, dt)
+            count = sizes[n]
+            nbytes = count * torch.empty(0, dtype=dtype).element_size()
+            spans.append((name, dtype, off, nbytes))
+            off += (nbytes + 255) // 256 * 256
+        buf = torch.empty(off, dtype=torch.uint8, device=device, pin_memory=pin)
+        return buf, {name: buf[o:o + nb].view(dtype) for name, dtype, o, nb in spans}
 
     def __init__(self, torch, dev, chunk, J, R):
-        pin = dict(pin_memory=True)
-        self.h = {"q": torch.zeros(R * chunk, dtype=torch.float32, **pin),
-                  "q_off": torch.zeros(J, dtype=torch.int64, **pin), "q_len": torch.zeros(J, dtype=torch.int32, **pin),
-                  "r_off": torch.zeros(J, dtype=torch.int64, **pin), "r_len": torch.zeros(J, dtype=torch.int32, **pin),
-                  "row_off": torch.zeros(J, dtype=torch.int64, **pin), "first": torch.zeros(J, dtype=torch.uint8, **pin),
-                  "cand_off": torch.zeros(R, dtype=torch.int64, **pin), "cand_cnt": torch.zeros(R, dtype=torch.int32, **pin),
-                  "n_events": torch.zeros(R, dtype=torch.int32, **pin)}
-        self.d = {k: torch.empty_like(v, device=dev) for k, v in self.h.items()}
-        self.d_out = {"score": torch.empty(J, dtype=torch.float32, device=dev),
-                      "end": torch.empty(J, dtype=torch.int32, device=dev),
-                      "best": torch.empty(R, dtype=torch.int32, device=dev),
-                      "best_score": torch.empty(R, dtype=torch.float64, device=dev),
-                      "mapped": torch.empty(R, dtype=torch.uint8, device=dev)}
-        self.h_out = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in self.d_out.items()}
+        sizes = {"R*chunk": R * chunk, "J": J, "R": R}
+        self.h_buf, self.h = self._views(torch, self.IN, sizes, "cpu", True)
+        self.d_buf, self.d = self._views(torch, self.IN, sizes, dev, False)
+        self.do_buf, self.d_out = self._views(torch, self.OUT, sizes, dev, False)
+        self.ho_buf, self.h_out = self._views(torch, self.OUT, sizes, "cpu", True)
+        self.h_buf.zero_()
         self.stream = torch.cuda.Stream()
         self.start = torch.cuda.Event(enable_timing=True)
         self.event = torch.cuda.Event(enable_timing=True)
@@ -411,14 +423,12 @@ class GpuBackend:
 
     def _work(self, sl: _Slot, b_match, threshold):
         d, o = sl.d, sl.d_out
-        for k in sl.h:
-            d[k].copy_(sl.h[k], non_blocking=True)
+        sl.d_buf.copy_(sl.h_buf, non_blocking=True)
         self.lib.rawalign_dtw_extend(d["q"], d["q_off"], d["q_len"], self.r, d["r_off"], d["r_len"], self.rows,
                                      d["row_off"], d["first"], o["score"], o["end"], opts=self.opts)
         self.lib.rawalign_decide(o["score"], d["cand_off"], d["cand_cnt"], d["n_events"], o["best"],
                                  o["best_score"], o["mapped"], b_match=b_match, threshold=threshold)
-        for k in o:
-            sl.h_out[k].copy_(o[k], non_blocking=True)
+        sl.ho_buf.copy_(sl.do_buf, non_blocking=True)
 
     def _fill(self, sl: _Slot, b: TickBatch):
         h = sl.h
@@ -509,15 +519,17 @@ class GpuBackend:
 
 def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
           max_jobs: int = 8192, max_reads: int = 256, timeout: float | None = None, backend=None,
-          slots: int = 2):
+          slots: int = 2, opts=None):
     """Run a workloads.ServingWorkload through the engine on the GPU.
     time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
-    period becomes 10 ms); slots is the number of ticks in flight.
+    period becomes 10 ms); slots is the number of ticks in flight; opts
+    (lib.Opts) goes to the extension call.
     max_jobs/max_reads size the per-tick tables (a captured tick copies them
     whole); chunks beyond them wait for the next tick."""
     arena_floats = arena_bytes // 4
     if backend is None:
-        backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph, slots=slots)
+        backend = GpuBackend(workload.r, arena_floats, workload.chunk, max_jobs, max_reads, use_graph, opts=opts,
+                             slots=slots)
     # The engine's clock starts at zero when the loop starts, after every read
     # has been submitted (submitting many reads takes a while itself).
     origin = [time.perf_counter()]

@@ -129,8 +129,8 @@ def _oracle_engine(wl):
     return eng
 
 
-@pytest.mark.parametrize("use_graph,slots", [(True, 2), (False, 2), (True, 1)])
-def test_serving_loop_matches_oracle_engine(L, use_graph, slots):
+@pytest.mark.parametrize("use_graph,slots,streams", [(True, 2, 1), (False, 2, 1), (True, 1, 1), (True, 2, 3)])
+def test_serving_loop_matches_oracle_engine(L, use_graph, slots, streams):
     """The serving loop on the GPU (real clock, time-compressed arrivals,
     graph-replayed or eager ticks, one or two ticks in flight) returns for
     every read and chunk exactly what the oracle-backed engine returns,
@@ -138,9 +138,9 @@ def test_serving_loop_matches_oracle_engine(L, use_graph, slots):
     from paper_2310_05037_amd import serve
     wl = W.serving_workload(60, rate=200.0, chunk=400, max_chunks=4, max_cands=8, ref_bases=200_000,
                             period=1.0, seed_index=33)
-    _say(f"  gpu: serving reads={len(wl.reads)} graph={use_graph} slots={slots}")
+    _say(f"  gpu: serving reads={len(wl.reads)} graph={use_graph} slots={slots} streams={streams}")
     eng, st = serve.serve(wl, arena_bytes=64 << 20, time_scale=0.02, use_graph=use_graph, max_jobs=1024,
-                          max_reads=128, timeout=120, slots=slots)
+                          max_reads=128, timeout=120, slots=slots, opts=L.make_opts(streams=streams))
     print("serving", st)
     ref = _oracle_engine(wl)
     assert st["failed"] == 0 and st["ticks"] > 0
