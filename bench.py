@@ -82,7 +82,7 @@ def cpu_baseline(b, seconds: float):
             "sample": f"{done_pairs} random pairs ({done_cells:.3e} cells, {dt:.1f} s), float64 recurrence"}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_multi_config2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_multi_uneven_batch_traffic.txt")
 KERNEL_SOURCES = ["dtw_device.h", "dtw_multi.hip", "internal.h"]
 
 
@@ -228,7 +228,7 @@ def main():
     cus = props.multi_processor_count
     valu_peak = cus * LANES_PER_CU * CLOCK_HZ
 
-    b = workloads.config2()
+    b = workloads.uneven_batch()
     cells = b.cells
     rc = route_cells(b)
     db = lib.DeviceBatch(b)
@@ -309,7 +309,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "config2_uneven_batch", "pairs": b.n_pairs, "reads": int(len(b.cand_off)),
+        "config": {"workload": "uneven_batch_100000_pairs", "pairs": b.n_pairs, "reads": int(len(b.cand_off)),
                    "cells": cells, "route_cells": rc, "device": props.name, "cus": cus,
                    "opts": {k: v for k, v in tuned.as_dict().items()}, "autotune_ms": tune_ms},
         "plain": None if plain_gcups is None else

@@ -15,7 +15,8 @@ these generators stand in for them with the same structure:
 * a read is aligned against candidate regions (Sec. 2.1.3); one region per
   read contains the read's source window, the others are uniform decoys.
 
-Every configuration uses numpy's PCG64 with seed 2310050370 + its index.
+Every workload uses numpy's PCG64 with seed 2310050370 + its seed index
+(0 single read, 1 plain batch, 2 uneven batch, 3 serving, 4 long stress).
 Regions are (offset, length) slices of the one reference level array; the
 candidates of a read share the read's query slice.
 """
@@ -76,8 +77,8 @@ class Batch:
                 "cells": self.cells, "sha256": h.hexdigest(), **self.meta}
 
 
-def rng_for(config_index: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(SEED_BASE + config_index))
+def rng_for(seed_index: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + seed_index))
 
 
 def pore_model(rng) -> np.ndarray:
@@ -153,7 +154,7 @@ def _true_region(rng, span_start, span_len, m, L):
     return int(min(max(off, 0), max(L - m, 0)))
 
 
-def config0(seed_index: int = 0) -> Batch:
+def single_read(seed_index: int = 0) -> Batch:
     """Plain single read: 10 kb reference, one read from a random 500-base
     window, 10 candidate regions of 900 bases (1 true, 9 random)."""
     rng = rng_for(seed_index)
@@ -170,8 +171,8 @@ def config0(seed_index: int = 0) -> Batch:
     pairs = [(0, true_off, m, True)]
     for _ in range(9):
         pairs.append((0, int(rng.integers(0, L - m + 1)), m, False))
-    return _pack("config0_single_read", [ev], pairs, r,
-                 {"config": 0, "window_start": w0, "reference_bases": len(bases)})
+    return _pack("single_read", [ev], pairs, r,
+                 {"seed_index": 0, "window_start": w0, "reference_bases": len(bases)})
 
 
 def _batched(name, seed_index, n_pairs, ref_bases, n_sampler, cands_sampler, ratio_lo, ratio_hi,
@@ -199,23 +200,23 @@ def _batched(name, seed_index, n_pairs, ref_bases, n_sampler, cands_sampler, rat
     return _pack(name, reads, pairs, r, dict(meta or {}, reference_bases=ref_bases))
 
 
-def config1(n_pairs: int = 4096) -> Batch:
+def plain_batch(n_pairs: int = 4096) -> Batch:
     """Plain batched: n ~ U[200, 2000], m = floor(n * U[1.2, 2.0]), 10
     candidates per read (1 true, 9 decoys: about 90% decoys)."""
-    return _batched("config1_plain_batched", 1, n_pairs, 1_000_000,
-                    lambda g: g.integers(200, 2001), lambda g: 10, 1.2, 2.0, {"config": 1})
+    return _batched("plain_batch", 1, n_pairs, 1_000_000,
+                    lambda g: g.integers(200, 2001), lambda g: 10, 1.2, 2.0, {"seed_index": 1})
 
 
-def config2(n_pairs: int = 100_000) -> Batch:
+def uneven_batch(n_pairs: int = 100_000) -> Batch:
     """Uneven batch: n = clip(round(LogNormal(ln 1500, 0.6)), 100, 8000),
     m = floor(n * U[1.2, 3.0]), 1-50 candidates per read, 50M-base reference."""
     def n_samp(g):
         return int(np.clip(np.round(g.lognormal(np.log(1500.0), 0.6)), 100, 8000))
-    return _batched("config2_uneven_batch", 2, n_pairs, 50_000_000, n_samp,
-                    lambda g: g.integers(1, 51), 1.2, 3.0, {"config": 2})
+    return _batched("uneven_batch", 2, n_pairs, 50_000_000, n_samp,
+                    lambda g: g.integers(1, 51), 1.2, 3.0, {"seed_index": 2})
 
 
-def config4(n_pairs: int = 1024, n: int = 10_000, m: int = 20_000) -> Batch:
+def long_stress(n_pairs: int = 1024, n: int = 10_000, m: int = 20_000) -> Batch:
     """Long-problem stress: n = 10,000 events against m = 20,000 levels; every
     read has one candidate, true for even reads and a decoy for odd ones."""
     rng = rng_for(4)
@@ -232,7 +233,7 @@ def config4(n_pairs: int = 1024, n: int = 10_000, m: int = 20_000) -> Batch:
             pairs.append((k, _true_region(rng, start, span, m, L), m, True))
         else:
             pairs.append((k, int(rng.integers(0, L - m + 1)), m, False))
-    return _pack("config4_long_stress", reads, pairs, r, {"config": 4, "reference_bases": len(bases)})
+    return _pack("long_stress", reads, pairs, r, {"seed_index": 4, "reference_bases": len(bases)})
 
 
 def chain_ordered(b: Batch, seed: int = 0, p_true_first: float = 0.9) -> Batch:

@@ -72,7 +72,7 @@ def test_bnb_uneven_batch_matches_full_decision(L):
     """2,000 pairs of the uneven workload (1-50 candidates per read, regions
     up to 3x the read, multi-stripe regions, queries over several blocks),
     candidates in a synthetic chaining order."""
-    b = W.chain_ordered(W.config2(n_pairs=2000), seed=1)
+    b = W.chain_ordered(W.uneven_batch(n_pairs=2000), seed=1)
     s32, e32, _ = oracle.dtw_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
     for block_rows in (512, 64):
         s, e, ob, os_, om = _run_bnb(L, b, block_rows=block_rows)
@@ -84,7 +84,7 @@ def test_bnb_uneven_batch_matches_full_decision(L):
 def test_bnb_edge_cases(L):
     """A read without candidates, reads sharing a pair, a query longer than
     max_query, degenerate pairs, another match bonus and threshold."""
-    b = W.chain_ordered(W.config1(n_pairs=400), seed=2)
+    b = W.chain_ordered(W.plain_batch(n_pairs=400), seed=2)
     q_len = b.q_len.copy()
     b = W.Batch(b.name, b.q, b.r, b.q_off, q_len, b.r_off, b.r_len.copy(), b.cand_off, b.cand_cnt,
                 b.n_events, b.true_pair, b.meta)

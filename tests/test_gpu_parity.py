@@ -34,11 +34,11 @@ def _run(L, b, **kw):
     return db.results()
 
 
-def test_config0_single_read(L):
-    b = W.config0()
+def test_single_read(L):
+    b = W.single_read()
     s, e = _run(L, b)
     st = parity.check(b, s, e)
-    print("config0", st)
+    print("single_read", st)
     ps, pe = _run(L, b, plain=True)
     assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
     # the true candidate (pair 0) ends inside the read's source window
@@ -114,11 +114,11 @@ def test_degenerate_and_invalid_pairs(L):
                 assert sc[i] == exp[0] and en[i] == exp[1], (i, sc[i], en[i])
 
 
-def test_config1_full(L):
-    b = W.config1()
+def test_plain_batch_full(L):
+    b = W.plain_batch()
     s, e = _run(L, b)
     st = parity.check(b, s, e)
-    print("config1", st)
+    print("plain_batch", st)
     ps, pe = _run(L, b, plain=True)
     assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
 
@@ -171,10 +171,10 @@ def test_antidiag_kernel_against_oracle(L):
     parity.check(b, s, e)
 
 
-def test_config4_antidiag_equals_striped(L):
+def test_long_stress_antidiag_equals_striped(L):
     """Full 1,024 x (10,000 x 20,000) batch: anti-diagonal and lane-striped
     kernels give the same bits."""
-    b = W.config4()
+    b = W.long_stress()
     s, e = _run(L, b)
     s2, e2 = _run(L, b, long_kernel=L.LONG_ANTIDIAG)
     assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2)
@@ -193,22 +193,22 @@ def test_long_query_limit(L):
     parity.check(b, s, e, pairs=[1])
 
 
-def test_config4_long_stress_sampled(L):
+def test_long_stress_sampled(L):
     """Full 1,024 x (10,000 x 20,000) batch on the GPU, 16 pairs against the
     oracle."""
-    b = W.config4()
+    b = W.long_stress()
     s, e = _run(L, b)
     sample = np.arange(0, b.n_pairs, b.n_pairs // 16)[:16]
     st = parity.check(b, s, e, pairs=sample)
-    print("config4", st)
+    print("long_stress", st)
     assert np.isfinite(s).all() and (e >= 0).all() and (e < b.r_len).all()
 
 
-def test_config2_persistent_vs_plain_and_sample(L):
+def test_uneven_batch_persistent_vs_plain_and_sample(L):
     """Full 100,000-pair uneven batch: persistent (default and autotuned, the
     setting the benchmark times) and plain bit-identical, and a stratified
     sample of 200 pairs against the oracle."""
-    b = W.config2()
+    b = W.uneven_batch()
     db = L.DeviceBatch(b)
     _say(f"  gpu: {b.name} persistent")
     db.run(opts=L.make_opts())
@@ -225,7 +225,7 @@ def test_config2_persistent_vs_plain_and_sample(L):
     assert np.array_equal(s.view(np.uint32), ts.view(np.uint32)) and np.array_equal(e, te), best.as_dict()
     sample = parity.stratified_sample(b, 200)
     st = parity.check(b, s, e, pairs=sample)
-    print("config2", st)
+    print("uneven_batch", st)
     assert np.isfinite(s).all() and (e >= 0).all() and (e < b.r_len).all()
 
 
@@ -242,7 +242,7 @@ def test_exact_inputs_match_double(L):
 def test_decide_matches_oracle(L):
     import torch
     from oracle import oracle
-    b = W.config1(n_pairs=600)
+    b = W.plain_batch(n_pairs=600)
     s32, _, _ = oracle.dtw_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
     s32 = s32.copy()
     s32[5] = np.inf  # a candidate with an empty region
@@ -269,7 +269,7 @@ def test_autotune_and_tuning_cache(L, tmp_path):
     """The autotuner picks a valid setting, writes it to a cache that loads
     back to the same setting, and the tuned path (opts NULL) gives the same
     bits as the defaults."""
-    b = W.config1(n_pairs=1500)
+    b = W.plain_batch(n_pairs=1500)
     db = L.DeviceBatch(b)
     _say(f"  gpu: autotune {b.name} pairs={b.n_pairs}")
     db.run(opts=L.make_opts())

@@ -166,7 +166,7 @@ def test_chain_order_keeps_reads_and_places_true_region():
     """The synthetic chaining order permutes candidates only within their
     read, keeps every pair, and puts the true region first for about the
     requested share of reads."""
-    b = W.config1(n_pairs=2000)
+    b = W.plain_batch(n_pairs=2000)
     c = W.chain_ordered(b, seed=3, p_true_first=0.8)
     assert np.array_equal(c.cand_off, b.cand_off) and np.array_equal(c.cand_cnt, b.cand_cnt)
     for k in range(len(b.cand_off)):
