@@ -131,7 +131,7 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
-def serving_leg(n_reads: int, rate: float, streams: int = 3):
+def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3):
     """Read Until serving at a fixed arrival rate, in real time: 400-event
     chunks one second apart, up to 10 chunks and 1-50 candidates per read,
     resident rows in an 8 GiB arena, two ticks in flight, each a captured
@@ -140,13 +140,13 @@ def serving_leg(n_reads: int, rate: float, streams: int = 3):
     from paper_2310_05037_amd import lib, serve, workloads
     opts = lib.make_opts(streams=streams)
     warm = workloads.serving_workload(300, rate=rate, seed_index=103)
-    serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120, opts=opts)
+    serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120, opts=opts, slots=slots)
     wl = workloads.serving_workload(n_reads, rate=rate)
-    _, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600, opts=opts)
+    _, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600, opts=opts, slots=slots)
     keep = ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "reads", "ticks", "jobs", "mapped", "unmapped",
             "failed", "peak_arena_bytes", "wall_s", "gcups", "chunks_per_s", "worst_ms", "tick_device_ms")
     out = {k: st[k] for k in keep if k in st}
-    out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period, "streams": streams,
+    out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period, "streams": streams, "slots": slots,
                 "latency": "decision on host minus the moment the chunk was available"})
     return out
 
@@ -206,6 +206,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="time the library defaults instead of tuned settings")
     ap.add_argument("--serving-reads", type=int, default=20000, help="reads in the serving leg (0: skip it)")
     ap.add_argument("--serving-rate", type=float, default=2000.0)
+    ap.add_argument("--serving-slots", type=int, default=3, help="serving ticks in flight")
     ap.add_argument("--serving-streams", type=int, default=3, choices=(1, 3),
                     help="library streams for the serving extension (3: the three route kernels concurrently)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -324,7 +325,7 @@ def main():
     del db
     torch.cuda.empty_cache()
     if args.serving_reads > 0:
-        out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams)
+        out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams, args.serving_slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -519,7 +519,7 @@ class GpuBackend:
 
 def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
           max_jobs: int = 8192, max_reads: int = 256, timeout: float | None = None, backend=None,
-          slots: int = 2, opts=None):
+          slots: int = 3, opts=None):
     """Run a workloads.ServingWorkload through the engine on the GPU.
     time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
     period becomes 10 ms); slots is the number of ticks in flight; opts
