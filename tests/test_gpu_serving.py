@@ -149,3 +149,33 @@ def test_serving_loop_matches_oracle_engine(L, use_graph, slots, streams):
         for x, y in zip(a.results, b.results):
             assert x[0] == y[0] and x[1] == y[1] and x[2] == y[2]
             assert np.array_equal(x[3].view(np.uint32), y[3].view(np.uint32)) and np.array_equal(x[4], y[4])
+
+
+def test_extend_edge_cases(L):
+    """A job whose row slot leaves the arena gets the sentinel and writes
+    nothing; an empty chunk on a stored row reports that row's minimum and
+    leaves it unchanged; an empty chunk with no events seen gives (0, -1);
+    an empty region gives (+inf, -1)."""
+    import torch
+    rng = np.random.default_rng(23)
+    ms = np.array([300, 5000, 300, 300, 0], np.int32)
+    r_np = rng.standard_normal(int(ms.sum()) + 1).astype(np.float32)
+    r_off = np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64)
+    rows_np = np.abs(rng.standard_normal(6000)).astype(np.float32)
+    rows = torch.from_numpy(rows_np.copy()).to("cuda")
+    row_off = np.array([5890, 0, 5000, 5400, 10], np.int64)   # job 0's slot ends past the arena
+    q = rng.standard_normal(100).astype(np.float32)
+    chunks = [q[:50], q[:60], np.zeros(0, np.float32), np.zeros(0, np.float32), q[:10]]
+    first = np.array([1, 1, 0, 1, 1], np.uint8)
+    sc, en = _extend_round(L, chunks, torch.from_numpy(r_np).to("cuda"), r_off, ms, rows, row_off, first)
+    after = rows.cpu().numpy()
+    assert np.isnan(sc[0]) and en[0] == -2
+    assert np.array_equal(after[5890:], rows_np[5890:])           # job 0 wrote nothing
+    from oracle import oracle
+    c32, e32 = oracle.dtw_f32(q[:60], r_np[r_off[1]:r_off[1] + ms[1]])
+    assert sc[1].view(np.uint32) == np.float32(c32).view(np.uint32) and en[1] == e32
+    stored = rows_np[5000:5300]                                     # job 2: empty chunk on a stored row
+    assert sc[2] == stored.min() and en[2] == int(np.argmin(stored))
+    assert np.array_equal(after[5000:5300], stored)
+    assert sc[3] == 0.0 and en[3] == -1                             # nothing seen yet
+    assert sc[4] == np.inf and en[4] == -1                          # empty region
