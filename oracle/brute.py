@@ -68,3 +68,32 @@ def brute_dtw(q, r):
         if i + 1 < n and j + 1 < m:
             stack.append((i + 1, j + 1, acc + abs(q[i + 1] - r[j + 1])))
     return best, best_end, count
+
+
+def brute_global_dtw(q, r):
+    """(cost, number of paths) of global DTW between two anchors by explicit
+    enumeration: every path starts at cell (0, 0), moves by (1,0), (0,1) or
+    (1,1) and stops at (n-1, m-1) (Sec. 2.4.2: the gap is entered and left
+    through the anchor corners).  Empty on both sides: (0, 1); empty on one
+    side only: (+inf, 0)."""
+    q = [float(x) for x in q]
+    r = [float(x) for x in r]
+    n, m = len(q), len(r)
+    if n == 0 or m == 0:
+        return (0.0, 1) if n == 0 and m == 0 else (math.inf, 0)
+    best = math.inf
+    count = 0
+    stack = [(0, 0, abs(q[0] - r[0]))]
+    while stack:
+        i, j, acc = stack.pop()
+        if i == n - 1 and j == m - 1:
+            count += 1
+            best = min(best, acc)
+            continue
+        if i + 1 < n:
+            stack.append((i + 1, j, acc + abs(q[i + 1] - r[j])))
+        if j + 1 < m:
+            stack.append((i, j + 1, acc + abs(q[i] - r[j + 1])))
+        if i + 1 < n and j + 1 < m:
+            stack.append((i + 1, j + 1, acc + abs(q[i + 1] - r[j + 1])))
+    return best, count

@@ -200,6 +200,86 @@ void oracle_dtw_matrix_f64(const float *q, int64_t n, const float *r, int64_t m,
     }
 }
 
+/*
+ * Global DTW between two anchors (Sec. 2.4.2, anchor-guided alignment).  The
+ * anchors of a chain are the cells at the upper-left and lower-right corners
+ * of a gap's table; the signals they cover are not aligned again.  So the
+ * path enters the gap diagonally from the upper-left anchor and leaves it
+ * diagonally into the lower-right one:
+ *
+ *   D(-1,-1) = 0,  D(-1,j) = +inf (j >= 0),  D(i,-1) = +inf (i >= 0)
+ *   D(i,j)   = c(i,j) + min{ D(i-1,j-1), D(i-1,j), D(i,j-1) }
+ *   G        = D(n-1, m-1)
+ *
+ * Degenerate gaps: n == m == 0 (the anchors touch diagonally) costs 0; a gap
+ * with events but no levels, or levels but no events, has no path through
+ * its own cells and costs +inf.  Returns NaN if memory runs out.
+ */
+double oracle_dtw_global_f64(const float *q, int64_t n, const float *r, int64_t m)
+{
+    if (n == 0 || m == 0)
+        return (n == 0 && m == 0) ? 0.0 : INFINITY;
+    double *prev = malloc((size_t)(m + 1) * sizeof(double));
+    double *cur = malloc((size_t)(m + 1) * sizeof(double));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return NAN;
+    }
+    /* prev[j+1] = D(i-1, j); prev[0] = D(i-1, -1). */
+    prev[0] = 0.0; /* the corner D(-1,-1) */
+    for (int64_t j = 0; j < m; ++j)
+        prev[j + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        double qi = (double)q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            double c = fabs(qi - (double)r[j]);
+            cur[j + 1] = c + min3_d(prev[j], prev[j + 1], cur[j]);
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    double g = prev[m];
+    free(prev);
+    free(cur);
+    return g;
+}
+
+/* The same recurrence with every value held in float. */
+float oracle_dtw_global_f32(const float *q, int64_t n, const float *r, int64_t m)
+{
+    if (n == 0 || m == 0)
+        return (n == 0 && m == 0) ? 0.0f : INFINITY;
+    float *prev = malloc((size_t)(m + 1) * sizeof(float));
+    float *cur = malloc((size_t)(m + 1) * sizeof(float));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return NAN;
+    }
+    prev[0] = 0.0f;
+    for (int64_t j = 0; j < m; ++j)
+        prev[j + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        float qi = q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            float d = qi - r[j];
+            float c = fabsf(d);
+            cur[j + 1] = c + min3_f(prev[j], prev[j + 1], cur[j]);
+        }
+        float *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    float g = prev[m];
+    free(prev);
+    free(cur);
+    return g;
+}
+
 /* ---- batches: pairs are independent, threads take pairs from a counter ---- */
 
 struct batch_job {
@@ -212,7 +292,8 @@ struct batch_job {
     int64_t n_pairs;
     double *out64;
     float *out32;
-    int32_t *out_end;
+    int32_t *out_end;   /* NULL for global alignment (no end column) */
+    int global;
     int64_t next;
 };
 
@@ -225,7 +306,12 @@ static void *batch_worker(void *arg)
             break;
         const float *qp = job->q + job->q_off[p];
         const float *rp = job->r + job->r_off[p];
-        if (job->out64)
+        if (job->global) {
+            if (job->out64)
+                job->out64[p] = oracle_dtw_global_f64(qp, job->q_len[p], rp, job->r_len[p]);
+            else
+                job->out32[p] = oracle_dtw_global_f32(qp, job->q_len[p], rp, job->r_len[p]);
+        } else if (job->out64)
             job->out64[p] = oracle_dtw_f64(qp, job->q_len[p], rp, job->r_len[p],
                                            NULL, NULL, &job->out_end[p]);
         else
@@ -264,7 +350,7 @@ int oracle_dtw_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, out_end, 0};
+                            out_score, NULL, out_end, 0, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -274,6 +360,25 @@ int oracle_dtw_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, out_end, 0};
+                            NULL, out_score, out_end, 0, 0};
+    return run_batch(&job, n_threads);
+}
+
+/* Global DTW (corner entry and exit) of every pair; no end column. */
+int oracle_dtw_global_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_len,
+                                const float *r, const int64_t *r_off, const int32_t *r_len,
+                                int64_t n_pairs, double *out_score, int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            out_score, NULL, NULL, 1, 0};
+    return run_batch(&job, n_threads);
+}
+
+int oracle_dtw_global_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_len,
+                                const float *r, const int64_t *r_off, const int32_t *r_len,
+                                int64_t n_pairs, float *out_score, int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            NULL, out_score, NULL, 1, 0};
     return run_batch(&job, n_threads);
 }

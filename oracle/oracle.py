@@ -11,6 +11,11 @@ with the HIP library.
 * ``decide``: the mapping decision of Sec. 2.3: Score = B_Match * N_Read -
   C_DTW per candidate, the highest score of a read is mapped iff it is at
   least Score_Threshold (defaults 0.4 and 20 from Sec. 3.1.5).
+* ``dtw_global_*`` / ``chain_costs`` / ``decide_chains``: anchor-guided
+  alignment of Sec. 2.4.2: every gap between two consecutive anchors of a
+  chain is aligned by global DTW entered and left through the anchor corners;
+  a chain's cost is the sum of its gaps' costs, taken in gap order; its Score
+  is B_Match times the events the chain aligns minus that cost.
 """
 from __future__ import annotations
 
@@ -62,6 +67,14 @@ def lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, i32p, ctypes.c_int]
+        L.oracle_dtw_global_f64.restype = ctypes.c_double
+        L.oracle_dtw_global_f64.argtypes = [f32p, i64, f32p, i64]
+        L.oracle_dtw_global_f32.restype = ctypes.c_float
+        L.oracle_dtw_global_f32.argtypes = [f32p, i64, f32p, i64]
+        for name, outp in (("oracle_dtw_global_batch_f64", f64p), ("oracle_dtw_global_batch_f32", f32p)):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -174,6 +187,99 @@ def decide(cost, cand_off, cand_cnt, n_events, b_match=B_MATCH, threshold=SCORE_
             s = b_match * N - float(cost[p])
             if best[k] < 0 or s > best_score[k]:
                 best[k] = p
+                best_score[k] = s
+        if best[k] >= 0 and best_score[k] >= threshold:
+            mapped[k] = 1
+    return best, best_score, mapped
+
+
+# ---- anchor-guided alignment (Sec. 2.4.2) ---------------------------------------
+
+def dtw_global_f64(q, r) -> float:
+    """Global DTW of one gap, entered and left through the anchor corners
+    (D(-1,-1) = 0, the rest of row -1 and column -1 +inf, result D(n-1, m-1));
+    0 when both sides are empty, +inf when only one is."""
+    q = _f32(q)
+    r = _f32(r)
+    return float(lib().oracle_dtw_global_f64(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r)))
+
+
+def dtw_global_f32(q, r) -> np.float32:
+    """The same recurrence with every value in float."""
+    q = _f32(q)
+    r = _f32(r)
+    return np.float32(lib().oracle_dtw_global_f32(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float),
+                                                  len(r)))
+
+
+def _global_batch(fn, dtype, q, q_off, q_len, r, r_off, r_len, threads):
+    q = _f32(q)
+    r = _f32(r)
+    q_off = np.ascontiguousarray(q_off, dtype=np.int64)
+    r_off = np.ascontiguousarray(r_off, dtype=np.int64)
+    q_len = np.ascontiguousarray(q_len, dtype=np.int32)
+    r_len = np.ascontiguousarray(r_len, dtype=np.int32)
+    n = len(q_off)
+    assert len(q_len) == n and len(r_off) == n and len(r_len) == n
+    assert n == 0 or (int((q_off + q_len).max()) <= len(q) and int(q_off.min()) >= 0)
+    assert n == 0 or (int((r_off + r_len).max()) <= len(r) and int(r_off.min()) >= 0)
+    out = np.empty(n, dtype=dtype)
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    used = 0
+    if n:
+        ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+        used = fn(_ptr(q, ctypes.c_float), _ptr(q_off, ctypes.c_int64), _ptr(q_len, ctypes.c_int32),
+                  _ptr(r, ctypes.c_float), _ptr(r_off, ctypes.c_int64), _ptr(r_len, ctypes.c_int32),
+                  n, _ptr(out, ct), int(threads))
+    return out, used
+
+
+def dtw_global_batch_f64(q, q_off, q_len, r, r_off, r_len, threads=None):
+    """Global DTW of every pair in double precision -> (costs f64, threads used)."""
+    return _global_batch(lib().oracle_dtw_global_batch_f64, np.float64, q, q_off, q_len, r, r_off, r_len, threads)
+
+
+def dtw_global_batch_f32(q, q_off, q_len, r, r_off, r_len, threads=None):
+    """Global DTW of every pair with float arithmetic -> (costs f32, threads used)."""
+    return _global_batch(lib().oracle_dtw_global_batch_f32, np.float32, q, q_off, q_len, r, r_off, r_len, threads)
+
+
+def chain_costs(gap_cost, chain_gap_off, chain_gap_cnt):
+    """Cost of every chain: the sum of its gaps' costs, added one gap after
+    another in gap order in the precision of `gap_cost` (float32 sums stay
+    float32).  A chain without gaps (a single anchor) costs 0; a chain whose
+    gap range leaves the gap array gets NaN."""
+    gap_cost = np.asarray(gap_cost)
+    dt = gap_cost.dtype.type
+    out = np.empty(len(chain_gap_off), dtype=gap_cost.dtype)
+    for c in range(len(chain_gap_off)):
+        g0, cnt = int(chain_gap_off[c]), int(chain_gap_cnt[c])
+        if cnt < 0 or g0 < 0 or g0 + cnt > len(gap_cost):
+            out[c] = np.nan
+            continue
+        acc = dt(0)
+        for g in range(g0, g0 + cnt):
+            acc = dt(acc + gap_cost[g])
+        out[c] = acc
+    return out
+
+
+def decide_chains(chain_cost, chain_events, cand_off, cand_cnt, b_match=B_MATCH, threshold=SCORE_THRESHOLD):
+    """Mapping decision of Sec. 2.3 over anchored candidates: candidate c of a
+    read scores b_match * chain_events[c] - chain_cost[c] (double precision),
+    where chain_events[c] counts the read events its chain aligns; the
+    highest score wins, the smallest candidate index on ties, and the read is
+    mapped iff that score >= threshold."""
+    n_reads = len(cand_off)
+    best = np.full(n_reads, -1, dtype=np.int32)
+    best_score = np.full(n_reads, -np.inf, dtype=np.float64)
+    mapped = np.zeros(n_reads, dtype=np.uint8)
+    for k in range(n_reads):
+        for c in range(int(cand_off[k]), int(cand_off[k]) + int(cand_cnt[k])):
+            s = b_match * float(chain_events[c]) - float(chain_cost[c])
+            if best[k] < 0 or s > best_score[k]:
+                best[k] = c
                 best_score[k] = s
         if best[k] >= 0 and best_score[k] >= threshold:
             mapped[k] = 1

@@ -16,7 +16,8 @@ these generators stand in for them with the same structure:
   read contains the read's source window, the others are uniform decoys.
 
 Every workload uses numpy's PCG64 with seed 2310050370 + its seed index
-(0 single read, 1 plain batch, 2 uneven batch, 3 serving, 4 long stress).
+(0 single read, 1 plain batch, 2 uneven batch, 3 serving, 4 long stress,
+5 anchored chains).
 Regions are (offset, length) slices of the one reference level array; the
 candidates of a read share the read's query slice.
 """
@@ -99,11 +100,13 @@ def expected_levels(bases: np.ndarray, model: np.ndarray) -> np.ndarray:
 
 
 def read_events(rng, levels: np.ndarray, start: int, n_events: int | None = None,
-                n_kmers: int | None = None) -> tuple[np.ndarray, int]:
+                n_kmers: int | None = None, trace: bool = False):
     """Events of a read whose first k-mer is levels[start].
 
     Either emit exactly `n_events` events (the read is cut there) or walk
-    `n_kmers` k-mers.  Returns (events float32, number of k-mers covered)."""
+    `n_kmers` k-mers.  Returns (events float32, number of k-mers covered), and
+    with `trace` also the events each covered k-mer emitted (int64, after the
+    cut); tracing draws no extra random numbers."""
     if n_kmers is None:
         guess = int(n_events / ((1 - SKIP_P) / DWELL_P)) + 64
         while True:
@@ -123,6 +126,9 @@ def read_events(rng, levels: np.ndarray, start: int, n_events: int | None = None
         dwell[rng.random(used) < SKIP_P] = 0
         lv = np.repeat(levels[start:start + used], dwell)
     ev = lv.astype(np.float64) + rng.normal(0.0, NOISE_SD, size=len(lv))
+    if trace:
+        emitted = np.diff(np.minimum(np.cumsum(dwell), len(lv)), prepend=0).astype(np.int64)
+        return ev.astype(np.float32), used, emitted
     return ev.astype(np.float32), used
 
 
@@ -334,3 +340,161 @@ def serving_workload(n_reads: int, rate: float = 2000.0, chunk: int = 400, max_c
             lens.append(m)
         reads.append(ServingRead(t, ev, np.array(offs, np.int64), np.array(lens, np.int32), 0))
     return ServingWorkload(r, reads, chunk, period, rate)
+
+
+# ---- anchored chains (Sec. 2.4.2): gaps between consecutive anchors ----
+
+ANCHOR_KMERS = (4, 12)      # k-mers one anchor covers, uniform inclusive
+GAP_MEAN_KMERS = 12.0       # k-mers between anchors: 1 + Geometric, this mean
+
+
+@dataclass
+class AnchoredBatch:
+    """Candidate chains of reads, reduced to the gaps between their anchors.
+
+    Gap g aligns q[gap_q_off[g] : +gap_q_len[g]] against
+    r[gap_r_off[g] : +gap_r_len[g]]; chain c owns gaps chain_gap_off[c] ..
+    +chain_gap_cnt[c] in chain order and aligns chain_events[c] read events
+    (first anchor's first event to last anchor's last); read k owns chains
+    cand_off[k] .. +cand_cnt[k]; true_chain[k] follows the read's source
+    window."""
+    name: str
+    q: np.ndarray
+    r: np.ndarray
+    gap_q_off: np.ndarray      # int64 per gap
+    gap_q_len: np.ndarray      # int32 per gap
+    gap_r_off: np.ndarray      # int64 per gap
+    gap_r_len: np.ndarray      # int32 per gap
+    chain_gap_off: np.ndarray  # int64 per chain
+    chain_gap_cnt: np.ndarray  # int32 per chain
+    chain_events: np.ndarray   # int32 per chain
+    cand_off: np.ndarray       # int64 per read
+    cand_cnt: np.ndarray       # int32 per read
+    true_chain: np.ndarray     # int64 per read
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_gaps(self) -> int:
+        return int(len(self.gap_q_off))
+
+    @property
+    def n_chains(self) -> int:
+        return int(len(self.chain_gap_off))
+
+    @property
+    def cells(self) -> int:
+        return int(np.dot(self.gap_q_len.astype(np.int64), self.gap_r_len.astype(np.int64)))
+
+
+def _anchor_walk(rng, n_kmers):
+    """Alternating anchors and gaps over k-mers 0..n_kmers-1, starting with an
+    anchor at k-mer 0, 1 or 2.  Returns a list of (first k-mer, end k-mer)
+    anchor intervals."""
+    anchors = []
+    u = int(rng.integers(0, 3))
+    gap_p = 1.0 / GAP_MEAN_KMERS
+    while True:
+        a = int(rng.integers(ANCHOR_KMERS[0], ANCHOR_KMERS[1] + 1))
+        if u + a > n_kmers:
+            break
+        anchors.append((u, u + a))
+        u += a + int(rng.geometric(gap_p))
+    return anchors
+
+
+def _chain_gaps(anchors, ev_at, lv_at):
+    """Gaps of a chain whose anchors are k-mer intervals; ev_at(u) / lv_at(u)
+    give the event / level offset where k-mer u starts.  A gap with events
+    but no levels (or levels but no events) has no path between the anchor
+    corners; such a gap is merged with the following anchor and gap.
+    Returns (list of (q offset, q length, r offset, r length), first event,
+    end event)."""
+    if not anchors:
+        return [], 0, 0
+    kept = [anchors[0]]
+    for a in anchors[1:]:
+        prev_end = kept[-1][1]
+        ng = ev_at(a[0]) - ev_at(prev_end)
+        mg = lv_at(a[0]) - lv_at(prev_end)
+        if (ng == 0) != (mg == 0):
+            continue      # drop this anchor: the gap runs on to the next one
+        kept.append(a)
+    gaps = []
+    for t in range(len(kept) - 1):
+        e0, e1 = ev_at(kept[t][1]), ev_at(kept[t + 1][0])
+        l0, l1 = lv_at(kept[t][1]), lv_at(kept[t + 1][0])
+        gaps.append((e0, e1 - e0, l0, l1 - l0))
+    return gaps, ev_at(kept[0][0]), ev_at(kept[-1][1])
+
+
+def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_index: int = 5) -> AnchoredBatch:
+    """Reads shaped like the uneven batch (n = clip(round(LogNormal(ln 1500,
+    0.6)), 100, 8000) events, 1-50 candidates per read, 50M-base reference),
+    each candidate reduced to a chain of anchors.
+
+    * The true candidate's anchors lie on the read's source path: anchors of
+      U{4..12} consecutive k-mers alternate with gaps of 1 + Geometric(1/12)
+      k-mers; an anchor covers the events its k-mers emitted.
+    * A decoy chain pairs a random stretch of the read (U[0.2, 1] of its
+      events) with a random stretch of the reference, with anchors and gaps
+      of the same k-mer statistics whose event counts are fresh dwell draws:
+      the same gap shapes, unrelated values.
+    """
+    rng = rng_for(seed_index)
+    model = pore_model(rng)
+    bases = random_bases(rng, ref_bases)
+    r = expected_levels(bases, model)
+    L = len(r)
+    reads = []
+    read_base = []
+    g_q_off, g_q_len, g_r_off, g_r_len = [], [], [], []
+    c_gap_off, c_gap_cnt, c_events = [], [], []
+    cand_cnt, true_chain = [], []
+    q_pos = 0
+    n_done = 0
+    while n_done < n_chains:
+        n = int(np.clip(np.round(rng.lognormal(np.log(1500.0), 0.6)), 100, 8000))
+        k = min(int(rng.integers(1, 51)), n_chains - n_done)
+        start = int(rng.integers(0, L - 4 * n))
+        ev, used, emitted = read_events(rng, r, start, n_events=n, trace=True)
+        ev_start = np.concatenate([[0], np.cumsum(emitted)]).astype(np.int64)
+        reads.append(ev)
+        read_base.append(q_pos)
+        true_chain.append(n_done)
+        for c in range(k):
+            if c == 0:
+                anchors = _anchor_walk(rng, used)
+                gaps, e_first, e_end = _chain_gaps(anchors, lambda u: int(ev_start[u]), lambda u: start + u)
+            else:
+                span = max(1, int(len(ev) * rng.uniform(0.2, 1.0)))
+                e0 = int(rng.integers(0, len(ev) - span + 1))
+                kmers = max(1, int(span / ((1 - SKIP_P) / DWELL_P)))
+                l0 = int(rng.integers(0, L - kmers + 1))
+                dwell = rng.geometric(DWELL_P, size=kmers)
+                dwell[rng.random(kmers) < SKIP_P] = 0
+                d_start = np.concatenate([[0], np.cumsum(dwell)]).astype(np.int64)
+                d_start = np.minimum(d_start, span)
+                anchors = _anchor_walk(rng, kmers)
+                gaps, e_first, e_end = _chain_gaps(anchors, lambda u: e0 + int(d_start[u]), lambda u: l0 + u)
+            c_gap_off.append(len(g_q_off))
+            c_gap_cnt.append(len(gaps))
+            c_events.append(e_end - e_first)
+            for (eo, el, lo, ll) in gaps:
+                g_q_off.append(q_pos + eo)
+                g_q_len.append(el)
+                g_r_off.append(lo)
+                g_r_len.append(ll)
+        cand_cnt.append(k)
+        q_pos += len(ev)
+        n_done += k
+    q = np.concatenate(reads).astype(np.float32)
+    cand_cnt = np.array(cand_cnt, dtype=np.int32)
+    cand_off = np.concatenate([[0], np.cumsum(cand_cnt)[:-1]]).astype(np.int64)
+    return AnchoredBatch("anchored_chains", q, r,
+                         np.array(g_q_off, dtype=np.int64), np.array(g_q_len, dtype=np.int32),
+                         np.array(g_r_off, dtype=np.int64), np.array(g_r_len, dtype=np.int32),
+                         np.array(c_gap_off, dtype=np.int64), np.array(c_gap_cnt, dtype=np.int32),
+                         np.array(c_events, dtype=np.int32), cand_off, cand_cnt,
+                         np.array(true_chain, dtype=np.int64),
+                         {"seed_index": seed_index, "reference_bases": ref_bases,
+                          "anchor_kmers": list(ANCHOR_KMERS), "gap_mean_kmers": GAP_MEAN_KMERS})
