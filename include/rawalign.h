@@ -219,6 +219,53 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
                      uint8_t *out_mapped, void *stream, const rawalign_opts *opts);
 
 /*
+ * Global DTW between two anchors (Sec. 2.4.2, anchor-guided alignment): a
+ * chain's anchors sit at the upper-left and lower-right corners of every gap
+ * between them, and the signals they cover are not aligned again, so the
+ * path enters the gap at (0, 0) from the corner D(-1,-1) = 0 and leaves at
+ * (n-1, m-1); the rest of row -1 and of column -1 is +inf.
+ *   Arguments as in rawalign_dtw_batch (device pointers, per-pair offset and
+ *   length), with
+ *   out_score  device float32 per pair: D(n-1, m-1)
+ *   out_end    device int32 per pair, may be NULL: m-1 (-1 for the
+ *              degenerate pairs below)
+ *   opts       mode and streams as in rawalign_dtw_batch_ex; long_kernel must
+ *              be RAWALIGN_LONG_STRIPED; NULL = defaults (not the tuned
+ *              settings)
+ * Pairs of at most 64 levels are aligned one pair per lane (grouped on the
+ * device by width and query length); wider ones by the striped kernels.
+ * Degenerate pairs: n == m == 0 (the anchors touch diagonally) costs 0;
+ * n == 0 or m == 0 alone costs +inf (no path through the gap's own cells).
+ * Invalid slices get NaN (end -2), as in rawalign_dtw_batch.  Scratch as in
+ * rawalign_dtw_batch, plus 4 bytes per pair for the per-lane planning.
+ */
+int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                              int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                              const rawalign_opts *opts);
+
+/*
+ * Chain sums and the mapping decision over anchored candidates (Sec. 2.4.2
+ * with Sec. 2.3):
+ *   - chain c owns gaps chain_gap_off[c] .. +chain_gap_cnt[c]; its cost is
+ *     the float sum of those gaps' costs, added in gap order
+ *     (out_chain_cost; 0 without gaps, NaN if the range leaves [0, n_gaps));
+ *   - read k owns chains cand_off[k] .. +cand_cnt[k]; chain c scores
+ *     b_match * chain_events[c] - cost (double), where chain_events counts
+ *     the read events the chain aligns; the highest score wins (smallest
+ *     chain index on ties) and the read is mapped iff it is >= threshold.
+ *   gap_cost (n_gaps floats, e.g. from rawalign_dtw_global_batch),
+ *   chain_gap_off int64, chain_gap_cnt/chain_events int32 per chain,
+ *   cand_off int64, cand_cnt int32 per read; outputs as in rawalign_decide
+ *   (out_best is a chain index).  All device pointers, async on `stream`.
+ */
+int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
+                          const int32_t *chain_gap_cnt, const int32_t *chain_events, int64_t n_chains,
+                          const int64_t *cand_off, const int32_t *cand_cnt, int64_t n_reads, double b_match,
+                          double threshold, float *out_chain_cost, int32_t *out_best, double *out_best_score,
+                          uint8_t *out_mapped, void *stream);
+
+/*
  * Autotuner: times candidate settings (persistent grid sizes of the three
  * kernels, concurrent or sequential kernels) on the caller's device batch
  * (same layout as rawalign_dtw_batch; out_score/out_end are scratch outputs)

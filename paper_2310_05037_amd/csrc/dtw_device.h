@@ -151,7 +151,8 @@ struct PairView {
     const float *r;
     int m;
     float *row;   // resident row (streaming) or null
-    bool fresh;   // row -1 is all zero
+    bool fresh;   // row -1 is all zero (subsequence) or the global boundary
+    bool global;  // corner entry at (0, 0), exit at (n-1, m-1)
 };
 
 template <bool EXT>
@@ -163,12 +164,38 @@ RA_DEV PairView pair_view(const PairArrays &a, int p) {
     pv.m = a.r_len[p];
     pv.row = EXT ? a.rows + a.row_off[p] : nullptr;
     pv.fresh = EXT ? a.first_chunk[p] != 0 : true;
+    pv.global = !EXT && a.global != 0;
     return pv;
+}
+
+// Slices inside q and r (and the resident row), lengths within the limits
+// of the striped kernels.
+RA_DEV bool slices_ok(const PairArrays &a, int64_t p, bool extend) {
+    const int n = a.q_len[p];
+    const int m = a.r_len[p];
+    const int64_t qo = a.q_off[p];
+    const int64_t ro = a.r_off[p];
+    bool ok = n >= 0 && m >= 0 && qo >= 0 && ro >= 0 && qo + n <= a.q_size && ro + m <= a.r_size &&
+              m <= kMaxRegion && n <= kMaxQuery && (m <= kSingleMaxRegion || n <= kEdgeCap);
+    if (extend) {
+        const int64_t wo = a.row_off[p];
+        ok = ok && wo >= 0 && wo + m <= a.rows_size;
+    }
+    return ok;
+}
+
+// A valid global pair narrow enough for one lane (dtw_global.hip).
+RA_DEV bool tiny_pair(const PairArrays &a, int64_t p) {
+    const int n = a.q_len[p];
+    const int m = a.r_len[p];
+    return a.global && n >= 1 && m >= 1 && m <= kTinyMaxCols && slices_ok(a, p, false);
 }
 
 // Registers of one lane: levels, the double-buffered DP row.  Columns are
 // tested against lim = m - col0 (one register) rather than by their index,
-// so no per-column index stays live through the sweep.
+// so no per-column index stays live through the sweep.  Row -1 is zero for
+// a fresh subsequence alignment, +inf for a global one (its corner
+// D(-1,-1) = 0 enters through lane 0's north-west value instead).
 template <int C, bool EXT>
 RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C], float (&B)[C]) {
     const int lim = pv.m - col0;
@@ -176,12 +203,13 @@ RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C
     const __amdgpu_buffer_rsrc_t rrs = make_rsrc(pv.r, pv.m);
     __amdgpu_buffer_rsrc_t wrs = rrs;
     if (EXT) wrs = make_rsrc(pv.row, pv.m);
+    const float row0 = pv.global ? kInf : 0.0f;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
         const int jc = col0 + (s < last ? s : last);   // clamped into the region
         const float lv = bload(rrs, jc);
         rv[s] = s < lim ? lv : 0.0f;   // padding columns: finite, never reported
-        float init = 0.0f;
+        float init = row0;
         if (EXT && !pv.fresh) {
             const float iv = bload(wrs, jc);
             init = s < lim ? iv : 0.0f;
@@ -193,12 +221,18 @@ RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C
 
 // After the sweep every lane has had at least one step past its last row,
 // so A holds row n-1 (or row -1 when n == 0).  Reduce it and optionally
-// store it.
+// store it.  A global alignment reports column m-1 only.
 template <int C, bool EXT>
 RA_DEV void finish_lane(const PairView &pv, int col0, const float (&A)[C], float &best, int &bj) {
     const int lim = pv.m - col0;
     best = kInf;
     bj = 0x7fffffff;
+    if (!EXT && pv.global) {
+#pragma unroll
+        for (int s = 0; s < C; ++s)
+            if (s == lim - 1) take_min(best, bj, A[s], col0 + s);
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < C; ++s) {
         if (s < lim) {
@@ -209,8 +243,11 @@ RA_DEV void finish_lane(const PairView &pv, int col0, const float (&A)[C], float
 }
 
 // Two consecutive steps (t even: A -> B, t+1: B -> A).  EIN: lane 0's left
-// values e0/e1 come from the edge buffer (else +inf kept in E0/E1).  EOUT:
-// lane 63 writes its last column of the rows it finished to edge[].
+// values e0/e1 come from the edge buffer.  Else lane 0's E0 stays +inf
+// (column -1) and its E1 is refilled from E0, so E1's initial value (the
+// corner D(-1,-1), 0 for a global alignment) is used once, as row 0's
+// north-west value.  EOUT: lane 63 writes its last column of the rows it
+// finished to edge[].
 template <int C, bool MASKED, bool EIN, bool EOUT>
 RA_DEV void two_steps(int t, int n, int lane, const float (&rv)[C], float (&A)[C], float (&B)[C],
                       float &qv, float q0, float q1, float &E0, float &E1, float e0, float e1,
@@ -221,7 +258,7 @@ RA_DEV void two_steps(int t, int n, int lane, const float (&rv)[C], float (&A)[C
     else row_step<C>(rv, qv, E1, E0, A, B);
     if (EOUT && t >= 63 && t - 63 < n && lane == 63) edge[t - 63] = B[C - 1];
     qv = dpp_shr1(q1, qv);
-    E1 = dpp_shr1(EIN ? e1 : E1, B[C - 1]);
+    E1 = dpp_shr1(EIN ? e1 : E0, B[C - 1]);   // lane 0 without an edge: column -1, +inf
     if (MASKED) row_step_masked<C>((unsigned)(t + 1 - lane) < (unsigned)n, rv, qv, E0, E1, B, A);
     else row_step<C>(rv, qv, E0, E1, B, A);
     if (EOUT && t >= 62 && t - 62 < n && lane == 63) edge[t - 62] = A[C - 1];
@@ -242,7 +279,7 @@ RA_DEV void two_steps2(int t, int n, int lane, const float (&rv)[C], float (&A)[
                          rv, Qe, Qo, E1, E0, A, B);
     if (EOUT && t >= 127 && t - 127 < n && lane == 63) edge[t - 127] = B[C - 1];
     Qo = dpp_shr1(q1, Qo);
-    E1 = dpp_shr1(EIN ? e1 : E1, B[C - 1]);
+    E1 = dpp_shr1(EIN ? e1 : E0, B[C - 1]);
     row_step2<C, MASKED>((unsigned)(t + 1 - 2 * lane) < (unsigned)n, (unsigned)(t - 2 * lane) < (unsigned)n,
                          rv, Qo, Qe, E0, E1, B, A);
     if (EOUT && t >= 126 && t - 126 < n && lane == 63) edge[t - 126] = A[C - 1];
@@ -267,9 +304,10 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
     const int n = pv.n;
     if (n > 0) {
         // Left boundary of the region: D(i,-1) = +inf for every row.  At row
-        // 0 the corner D(-1,-1) may be 0, but then D(-1,0) = 0 as well, so
-        // +inf gives the same minimum.
-        float E0 = kInf, E1 = kInf, qv = 0.0f, qo = 0.0f;
+        // 0 the corner D(-1,-1) of a subsequence alignment may be 0, but then
+        // D(-1,0) = 0 as well, so +inf gives the same minimum; a global
+        // alignment enters through that corner, which is 0.
+        float E0 = kInf, E1 = pv.global ? 0.0f : kInf, qv = 0.0f, qo = 0.0f;
         if (EIN) E1 = corner;   // row 0's north-west neighbour left of this stripe
         const __amdgpu_buffer_rsrc_t qrs = make_rsrc(pv.q, n);
         const __amdgpu_buffer_rsrc_t ers = make_rsrc(edge, n);

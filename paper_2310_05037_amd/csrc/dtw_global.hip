@@ -1,0 +1,226 @@
+// dtw_global.hip -- anchor-guided alignment (RawAlign, arXiv 2310.05037,
+// Sec. 2.4.2): global DTW of the gaps between consecutive anchors of a chain,
+// and the sums of a chain's gap costs.
+//
+// A gap is entered diagonally from the upper-left anchor and left diagonally
+// into the lower-right one: D(-1,-1) = 0, the rest of row -1 and column -1
+// are +inf, and the gap costs D(n-1, m-1).  Gaps are short (tens of events
+// against a few to a few dozen levels), far too narrow for a 64-lane stripe,
+// so here one lane aligns one gap:
+//   * the gap's levels and a double-buffered DP row sit in the lane's VGPRs,
+//     right-aligned in W slots (W = 4 .. 64), so the result D(n-1, m-1) is
+//     always slot W-1;
+//   * the W-m slots on the left hold +inf levels: their cells stay +inf and
+//     act as column -1; row -1 is +inf except the corner D(-1,-1) = 0 in
+//     slot W-m-1 (or left of slot 0 when m == W);
+//   * every cell is one v_sub_f32, one v_min3_f32 and one v_add_f32 with an
+//     |x| modifier, with no cross-lane traffic at all;
+//   * the lanes of a wave take gaps of one width class with similar query
+//     lengths (planned on the device: width class, then quarter octaves of
+//     n, longest first), so little of a wave idles.
+// Gaps wider than 64 levels go to the striped kernels in global mode.
+#include "dtw_device.h"
+
+namespace ra {
+
+constexpr int kTinyBins = kTinyClasses * kTinyBuckets;   // 1024
+constexpr int kTinyPlanBlock = 256;
+
+RA_DEV int tiny_class(int m) {
+    int c = 0;
+    while (c < kTinyClasses - 1 && tiny_width(c) < m) ++c;
+    return c;
+}
+
+// Width class, then query length in quarter octaves, longest first.
+RA_DEV int tiny_bin(int n, int m) {
+    int b = (int)(4.0f * __log2f((float)n));
+    b = b < 0 ? 0 : (b >= kTinyBuckets ? kTinyBuckets - 1 : b);
+    return tiny_class(m) * kTinyBuckets + (kTinyBuckets - 1 - b);
+}
+
+__global__ void k_tiny_zero(TinyScratch t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kTinyBins) t.hist[i] = 0;
+    if (i < kTinyClasses) {
+        t.counts[i] = 0;
+        t.base[i] = 0;
+    }
+}
+
+// Per-workgroup histogram in LDS, one global atomic per non-empty bin.
+__global__ __launch_bounds__(kTinyPlanBlock) void k_tiny_count(PairArrays a, int64_t n_pairs, TinyScratch t) {
+    __shared__ int h[kTinyBins];
+    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock) h[i] = 0;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_pairs && tiny_pair(a, p)) atomicAdd(&h[tiny_bin(a.q_len[p], a.r_len[p])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock)
+        if (h[i]) atomicAdd(&t.hist[i], h[i]);
+}
+
+// Exclusive scan of all bins in class-major order (one workgroup of
+// kTinyBins threads, Hillis-Steele in LDS): class c then occupies
+// list[base[c] .. base[c] + counts[c]).
+__global__ __launch_bounds__(kTinyBins) void k_tiny_scan(TinyScratch t) {
+    __shared__ int v[kTinyBins];
+    const int i = threadIdx.x;
+    const int own = t.hist[i];
+    v[i] = own;
+    __syncthreads();
+    for (int off = 1; off < kTinyBins; off <<= 1) {
+        const int x = i >= off ? v[i - off] : 0;
+        __syncthreads();
+        v[i] += x;
+        __syncthreads();
+    }
+    const int excl = v[i] - own;
+    t.hist[i] = excl;
+    if (i % kTinyBuckets == 0) t.base[i / kTinyBuckets] = excl;
+    if (i % kTinyBuckets == kTinyBuckets - 1) {
+        const int c = i / kTinyBuckets;
+        t.counts[c] = v[i] - (i + 1 - kTinyBuckets == 0 ? 0 : v[i - kTinyBuckets]);
+    }
+}
+
+// Each workgroup ranks its gaps per bin in LDS and reserves one contiguous
+// range per bin with a single global atomic on the bin's cursor.
+__global__ __launch_bounds__(kTinyPlanBlock) void k_tiny_scatter(PairArrays a, int64_t n_pairs, TinyScratch t) {
+    __shared__ int cnt[kTinyBins];
+    __shared__ int base[kTinyBins];
+    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock) cnt[i] = 0;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bin = -1, rank = 0;
+    if (p < n_pairs && tiny_pair(a, p)) {
+        bin = tiny_bin(a.q_len[p], a.r_len[p]);
+        rank = atomicAdd(&cnt[bin], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock)
+        if (cnt[i]) base[i] = atomicAdd(&t.hist[i], cnt[i]);
+    __syncthreads();
+    if (bin >= 0) t.list[base[bin] + rank] = (int32_t)p;
+}
+
+// One query row over the lane's W slots.  diag0: north-west value of slot 0
+// (the corner at row 0 when m == W, else +inf); west of slot 0 is +inf.
+template <int W>
+RA_DEV void tiny_row(float qv, float diag0, const float (&rv)[W], const float (&Ao)[W], float (&An)[W]) {
+    An[0] = fabsf(qv - rv[0]) + fminf(diag0, Ao[0]);
+#pragma unroll
+    for (int v = 1; v < W; ++v) An[v] = cell(qv, rv[v], Ao[v - 1], Ao[v], An[v - 1]);
+}
+
+// Gaps of width class `cls` (m <= W levels), 64 per wave, in list order.
+template <int W>
+__global__ __launch_bounds__(64) void k_tiny(PairArrays a, TinyScratch t, int cls) {
+    const int count = t.counts[cls];
+    const int32_t *list = t.list + t.base[cls];
+    const int lane = __lane_id();
+    for (int base = blockIdx.x * 64; base < count; base += gridDim.x * 64) {
+        const bool act = base + lane < count;
+        const int p = list[act ? base + lane : count - 1];   // idle lanes repeat the last gap
+        const int n = a.q_len[p];                            // >= 1
+        const int m = a.r_len[p];                            // 1 .. W
+        const float *qp = a.q + a.q_off[p];
+        const float *rp = a.r + a.r_off[p];
+        const int pad = W - m;
+        // Slot v holds level v - pad; slots left of the gap are never read
+        // from memory (the load is masked off for them).
+        const float *rs = rp - pad;
+        float rv[W], A[W], B[W];
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            rv[v] = v >= pad ? rs[v] : kInf;
+            A[v] = v == pad - 1 ? 0.0f : kInf;
+        }
+        float corner = pad == 0 ? 0.0f : kInf;
+        int nmax = n;   // the wave runs as long as its longest gap
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
+        float res = kInf;
+        float qa = qp[0];
+        for (int i = 0; i < nmax; i += 2) {
+            const float q0 = qa;
+            const float q1 = qp[i + 1 < n ? i + 1 : n - 1];
+            qa = qp[i + 2 < n ? i + 2 : n - 1];
+            tiny_row<W>(q0, corner, rv, A, B);
+            corner = kInf;
+            if (i == n - 1) res = B[W - 1];
+            tiny_row<W>(q1, kInf, rv, B, A);
+            if (i + 1 == n - 1) res = A[W - 1];
+        }
+        if (act) {
+            a.out_score[p] = res;
+            if (a.out_end) a.out_end[p] = m - 1;
+        }
+    }
+}
+
+template <int C>
+static int tiny_occupancy() {
+    static int occ = 0;
+    if (!occ) {
+        int nb = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiny<tiny_width(C)>, 64, 0);
+        occ = nb > 0 ? nb : 1;
+    }
+    return occ;
+}
+
+template <int C>
+static hipError_t launch_tiny_class(const PairArrays &a, const TinyScratch &t, int cus, hipStream_t stream) {
+    if constexpr (C < kTinyClasses) {
+        const unsigned grid = (unsigned)(cus * tiny_occupancy<C>());
+        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, stream, a, t, C);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_tiny_class<C + 1>(a, t, cus, stream);
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus, hipStream_t stream) {
+    hipLaunchKernelGGL(k_tiny_zero, dim3((kTinyBins + 255) / 256), dim3(256), 0, stream, t);
+    const unsigned g = (unsigned)((n_pairs + kTinyPlanBlock - 1) / kTinyPlanBlock);
+    hipLaunchKernelGGL(k_tiny_count, dim3(g), dim3(kTinyPlanBlock), 0, stream, a, n_pairs, t);
+    hipLaunchKernelGGL(k_tiny_scan, dim3(1), dim3(kTinyBins), 0, stream, t);
+    hipLaunchKernelGGL(k_tiny_scatter, dim3(g), dim3(kTinyPlanBlock), 0, stream, a, n_pairs, t);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tiny_class<0>(a, t, cus, stream);
+}
+
+// ---- chain sums ------------------------------------------------------------------
+
+// Chain c costs the sum of its gaps' costs, added one after another in gap
+// order (one float rounding per gap, the same order as a sequential sum).  A
+// chain without gaps costs 0; a gap range outside [0, n_gaps) gives NaN.
+__global__ void k_chain_sum(const float *__restrict__ gap_cost, int64_t n_gaps,
+                            const int64_t *__restrict__ chain_gap_off, const int32_t *__restrict__ chain_gap_cnt,
+                            int64_t n_chains, float *__restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chains) return;
+    const int64_t g0 = chain_gap_off[c];
+    const int cnt = chain_gap_cnt[c];
+    if (cnt < 0 || g0 < 0 || g0 + cnt > n_gaps) {
+        out[c] = __builtin_nanf("");
+        return;
+    }
+    float acc = 0.0f;
+    for (int g = 0; g < cnt; ++g) acc = acc + gap_cost[g0 + g];
+    out[c] = acc;
+}
+
+hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
+                            const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
+                            hipStream_t stream) {
+    const unsigned g = (unsigned)((n_chains + 255) / 256);
+    hipLaunchKernelGGL(k_chain_sum, dim3(g), dim3(256), 0, stream, gap_cost, n_gaps, chain_gap_off, chain_gap_cnt,
+                       n_chains, out_chain_cost);
+    return hipGetLastError();
+}
+
+}  // namespace ra

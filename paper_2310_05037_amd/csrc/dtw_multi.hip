@@ -62,7 +62,7 @@ void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__re
         multi_dispatch<kMultiMinH, EXT>(h, pv, S, edge, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
-            a.out_end[p] = bj;
+            if (a.out_end) a.out_end[p] = bj;
         }
         if (queue) {
             int it = 0;

@@ -14,25 +14,28 @@ struct PlanArgs {
 
 // Route of pair p.  Returns -1 when the pair needs no kernel; then
 // (score, end) is its result: a sentinel for invalid slices (NaN, -2) or the
-// value of a degenerate pair (empty query or empty region).
+// value of a degenerate pair (empty query or empty region).  Returns -2 for
+// a global pair that the one-pair-per-lane kernel aligns (no output here).
 RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
     const PairArrays &a = pa.a;
     const int n = a.q_len[p];
     const int m = a.r_len[p];
-    const int64_t qo = a.q_off[p];
-    const int64_t ro = a.r_off[p];
-    bool ok = n >= 0 && m >= 0 && qo >= 0 && ro >= 0 && qo + n <= a.q_size && ro + m <= a.r_size &&
-              m <= kMaxRegion && n <= kMaxQuery && (m <= kSingleMaxRegion || n <= kEdgeCap);
-    bool fresh = true;
-    if (pa.extend) {
-        const int64_t wo = a.row_off[p];
-        ok = ok && wo >= 0 && wo + m <= a.rows_size;
-        fresh = a.first_chunk[p] != 0;
-    }
+    const bool ok = slices_ok(a, p, pa.extend != 0);
+    const bool fresh = pa.extend ? a.first_chunk[p] != 0 : true;
     if (!ok) {
         score = __builtin_nanf("");
         end = -2;
         return -1;
+    }
+    if (a.global) {
+        // Anchors touching diagonally cost 0; a gap with events but no
+        // levels (or levels but no events) has no path: +inf.
+        if (n == 0 || m == 0) {
+            score = (n == 0 && m == 0) ? 0.0f : kInf;
+            end = -1;
+            return -1;
+        }
+        if (m <= kTinyMaxCols) return -2;
     }
     if (n == 0 && fresh) {
         score = 0.0f;
@@ -89,9 +92,9 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs pa) {
         const int route = classify(pa, p, b, sc, e);
         if (route >= 0) {
             atomicAdd(&h[route * kBuckets + b], 1);
-        } else {
+        } else if (route == -1) {
             pa.a.out_score[p] = sc;
-            pa.a.out_end[p] = e;
+            if (pa.a.out_end) pa.a.out_end[p] = e;
         }
     }
     __syncthreads();
@@ -161,7 +164,7 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
 __global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const int64_t *__restrict__ cand_off,
                          const int32_t *__restrict__ cand_cnt, const int32_t *__restrict__ n_events,
                          int64_t n_reads, double b_match, double threshold, int32_t *out_best,
-                         double *out_score, uint8_t *out_mapped) {
+                         double *out_score, uint8_t *out_mapped, bool per_candidate) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_reads) return;
     const int64_t p0 = cand_off[k];
@@ -173,11 +176,12 @@ __global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const
         return;
     }
     // Score = B_Match * N_Read - C_DTW; highest wins, smallest index on ties.
-    const double bonus = b_match * (double)n_events[k];
+    // Anchored chains count the events each chain aligns.
+    const double bonus = per_candidate ? 0.0 : b_match * (double)n_events[k];
     int32_t best = -1;
     double bs = -__builtin_inf();
     for (int c = 0; c < cnt; ++c) {
-        const double s = bonus - (double)score[p0 + c];
+        const double s = (per_candidate ? b_match * (double)n_events[p0 + c] : bonus) - (double)score[p0 + c];
         if (best < 0 || s > bs) {
             best = (int32_t)(p0 + c);
             bs = s;
@@ -190,10 +194,11 @@ __global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const
 
 hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
-                         int32_t *out_best, double *out_score, uint8_t *out_mapped, hipStream_t stream) {
+                         int32_t *out_best, double *out_score, uint8_t *out_mapped, bool per_candidate,
+                         hipStream_t stream) {
     const unsigned g = (unsigned)((n_reads + 255) / 256);
     hipLaunchKernelGGL(k_decide, dim3(g), dim3(256), 0, stream, score, n_pairs, cand_off, cand_cnt, n_events,
-                       n_reads, b_match, threshold, out_best, out_score, out_mapped);
+                       n_reads, b_match, threshold, out_best, out_score, out_mapped, per_candidate);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ void k_single(PairArrays a, const int32_t *__restrict__ list, const int32_t *__r
                         4 * KHI / kSingleColStep>(h, pv, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
-            a.out_end[p] = bj;
+            if (a.out_end) a.out_end[p] = bj;
         }
         if (!queue) break;
         int it = 0;

@@ -8,6 +8,8 @@
 
 namespace ra {
 
+#define RA_HOST_DEV __host__ __device__
+
 // Routes a pair can take after planning:
 //   single_lo: one stripe, 2..32 columns per lane (region <= 2048 levels)
 //   single_hi: one stripe, 34..64 columns per lane (region <= 4096 levels)
@@ -80,6 +82,27 @@ struct PairArrays {
     int64_t rows_size;
     const int64_t *row_off;
     const uint8_t *first_chunk;
+    // 1: global alignment between two anchors (Sec. 2.4.2): the path enters
+    // at (0, 0) from the corner D(-1,-1) = 0 and leaves at (n-1, m-1); the
+    // rest of row -1 is +inf.  0: subsequence alignment.
+    int global = 0;
+};
+
+// Global pairs of at most kTinyMaxCols levels are aligned one pair per lane
+// (dtw_global.hip); the planning of the striped kernels leaves them out.
+constexpr int kTinyClasses = 8;
+constexpr int kTinyMaxCols = 64;
+constexpr int kTinyBuckets = 128;   // quarter octaves of the query length
+RA_HOST_DEV constexpr int tiny_width(int c) {
+    return c == 0 ? 4 : c == 1 ? 8 : c == 2 ? 12 : c == 3 ? 16 : c == 4 ? 24 : c == 5 ? 32 : c == 6 ? 48 : 64;
+}
+
+struct TinyScratch {
+    int32_t *hist;      // [kTinyClasses * kTinyBuckets] histogram, then cursors
+    int32_t *counts;    // [kTinyClasses] pairs per width class
+    int32_t *base;      // [kTinyClasses] first list slot of each class
+    int32_t *list;      // [capacity] pair indices, class by class, longest queries first
+    int64_t capacity;
 };
 
 // Early termination (branch and bound): pair status and scratch.
@@ -128,9 +151,16 @@ hipError_t launch_antidiag(const PairArrays &a, int64_t n_pairs, const LaunchCfg
                            const PlanScratch &s, hipStream_t stream);
 hipError_t launch_bnb(const BnbArgs &b, int grid, float *edge, hipStream_t stream);
 int bnb_blocks_per_cu();
+// per_candidate: n_events holds one count per candidate (anchored chains)
+// instead of one per read.
 hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
-                         int32_t *out_best, double *out_score, uint8_t *out_mapped, hipStream_t stream);
+                         int32_t *out_best, double *out_score, uint8_t *out_mapped, bool per_candidate,
+                         hipStream_t stream);
+hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus, hipStream_t stream);
+hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
+                            const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
+                            hipStream_t stream);
 
 // Occupancy-derived resident workgroups per CU of each route's kernel.
 int single_lo_blocks_per_cu(bool extend);

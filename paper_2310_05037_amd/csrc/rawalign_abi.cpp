@@ -17,7 +17,7 @@
 #include "internal.h"
 #include "rawalign.h"
 
-#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.3.0"
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.4.0"
 
 namespace {
 
@@ -53,6 +53,9 @@ struct StreamScratch {
     int64_t edge_slots = 0;
     float *rowbuf = nullptr;    // anti-diagonal kernel only
     int64_t row_slots = 0;
+    int32_t *tiny_words = nullptr;   // one-pair-per-lane planning: hist | counts | base
+    int32_t *tiny_list = nullptr;
+    int64_t tiny_capacity = 0;
     hipStream_t sub[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr;
     hipEvent_t join[3] = {nullptr, nullptr, nullptr};
@@ -169,6 +172,44 @@ int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots
     return RAWALIGN_OK;
 }
 
+// Planning scratch of the one-pair-per-lane kernel (global calls only).
+int get_tiny(StreamScratch &s, int64_t n_pairs) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipError_t e;
+    if (!s.tiny_words) {
+        const size_t words = (size_t)ra::kTinyClasses * ra::kTinyBuckets + 2 * ra::kTinyClasses;
+        e = hipMalloc((void **)&s.tiny_words, words * sizeof(int32_t));
+        if (e != hipSuccess) {
+            s.tiny_words = nullptr;
+            return alloc_fail(e);
+        }
+    }
+    if (s.tiny_capacity < n_pairs) {
+        int64_t cap = s.tiny_capacity ? s.tiny_capacity : 1024;
+        while (cap < n_pairs) cap *= 2;
+        if (s.tiny_list) (void)hipFree(s.tiny_list);
+        s.tiny_list = nullptr;
+        s.tiny_capacity = 0;
+        e = hipMalloc((void **)&s.tiny_list, (size_t)cap * sizeof(int32_t));
+        if (e != hipSuccess) {
+            s.tiny_list = nullptr;
+            return alloc_fail(e);
+        }
+        s.tiny_capacity = cap;
+    }
+    return RAWALIGN_OK;
+}
+
+ra::TinyScratch tiny_view(StreamScratch &s) {
+    ra::TinyScratch t;
+    t.hist = s.tiny_words;
+    t.counts = s.tiny_words + ra::kTinyClasses * ra::kTinyBuckets;
+    t.base = t.counts + ra::kTinyClasses;
+    t.list = s.tiny_list;
+    t.capacity = s.tiny_capacity;
+    return t;
+}
+
 ra::PlanScratch plan_view(StreamScratch &s) {
     ra::PlanScratch p;
     p.hist = s.words;
@@ -221,6 +262,7 @@ struct Call {
     const int64_t *row_off;
     const uint8_t *first_chunk;
     hipStream_t stream;
+    bool global = false;   // global alignment between anchors (Sec. 2.4.2)
 };
 
 int check_call(const Call &c) {
@@ -230,7 +272,7 @@ int check_call(const Call &c) {
     if (c.q_size >= ((int64_t)1 << 40) || c.r_size >= ((int64_t)1 << 40))
         return fail(RAWALIGN_EINVAL, "q_size and r_size must be < 2^40");
     if (c.n_pairs == 0) return RAWALIGN_OK;
-    if (!c.q_off || !c.q_len || !c.r_off || !c.r_len || !c.out_score || !c.out_end)
+    if (!c.q_off || !c.q_len || !c.r_off || !c.r_len || !c.out_score || (!c.out_end && !c.global))
         return fail(RAWALIGN_EINVAL, "null pointer argument");
     if ((c.q_size > 0 && !c.q) || (c.r_size > 0 && !c.r)) return fail(RAWALIGN_EINVAL, "null data pointer");
     if (c.rows && (!c.row_off || !c.first_chunk || c.rows_size < 0))
@@ -247,6 +289,8 @@ int run(const Call &c, const rawalign_opts &o) {
     if (rc) return rc;
     if (c.rows && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
         return fail(RAWALIGN_EINVAL, "extend: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
+    if (c.global && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
+        return fail(RAWALIGN_EINVAL, "global alignment: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
     if (c.n_pairs == 0) return RAWALIGN_OK;
     int dev = 0;
     DeviceInfo info;
@@ -287,12 +331,21 @@ int run(const Call &c, const rawalign_opts &o) {
     a.rows_size = c.rows_size;
     a.row_off = c.row_off;
     a.first_chunk = c.first_chunk;
+    a.global = c.global ? 1 : 0;
     const ra::PlanScratch ps = plan_view(*s);
+    if (c.global) {
+        rc = get_tiny(*s, c.n_pairs);
+        if (rc) return rc;
+    }
 
     hipError_t e;
     if (timing && (e = hipEventRecord(s->ev[0], c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "plan kernels");
+    if (c.global) {
+        e = ra::launch_tiny(a, c.n_pairs, tiny_view(*s), info.cus, c.stream);
+        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
+    }
     if (timing) (void)hipEventRecord(s->ev[1], c.stream);
     hipStream_t st[3] = {c.stream, c.stream, c.stream};
     if (concurrent) {
@@ -531,7 +584,7 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
     }
     if (n_reads > 0) {
         e = ra::launch_decide(out_score, n_pairs, cand_off, cand_cnt, n_events, n_reads, b_match, threshold, out_best,
-                              out_best_score, out_mapped, st);
+                              out_best_score, out_mapped, false, st);
         if (e != hipSuccess) return hip_fail(e, "decide kernel");
     }
     return RAWALIGN_OK;
@@ -552,8 +605,53 @@ int rawalign_decide(const float *score, int64_t n_pairs, const int64_t *cand_off
     int rc = device_info(dev, info);
     if (rc) return rc;
     hipError_t e = ra::launch_decide(score, n_pairs, cand_off, cand_cnt, n_events, n_reads, b_match, threshold,
-                                     out_best, out_score, out_mapped, (hipStream_t)stream);
+                                     out_best, out_score, out_mapped, false, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "decide kernel");
+    return RAWALIGN_OK;
+}
+
+int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                              int64_t n_pairs, float *out_score, int32_t *out_end, void *stream,
+                              const rawalign_opts *opts) {
+    rawalign_opts o;
+    defaults(o);
+    if (opts) o = *opts;
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream, true};
+    return run(c, o);
+}
+
+int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
+                          const int32_t *chain_gap_cnt, const int32_t *chain_events, int64_t n_chains,
+                          const int64_t *cand_off, const int32_t *cand_cnt, int64_t n_reads, double b_match,
+                          double threshold, float *out_chain_cost, int32_t *out_best, double *out_best_score,
+                          uint8_t *out_mapped, void *stream) {
+    if (n_gaps < 0 || n_chains < 0 || n_reads < 0)
+        return fail(RAWALIGN_EINVAL, "n_gaps, n_chains and n_reads must be >= 0");
+    if (n_chains > 0 && (!chain_gap_off || !chain_gap_cnt || !chain_events || !out_chain_cost))
+        return fail(RAWALIGN_EINVAL, "null chain pointer argument");
+    if (n_gaps > 0 && !gap_cost) return fail(RAWALIGN_EINVAL, "null gap_cost");
+    if (n_reads > 0 && (!cand_off || !cand_cnt || !out_best || !out_best_score || !out_mapped))
+        return fail(RAWALIGN_EINVAL, "null read pointer argument");
+    if (!std::isfinite(b_match) || std::isnan(threshold))
+        return fail(RAWALIGN_EINVAL, "b_match must be finite and threshold not NaN");
+    if (n_chains == 0 && n_reads == 0) return RAWALIGN_OK;
+    int dev = 0;
+    DeviceInfo info;
+    int rc = device_info(dev, info);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (n_chains > 0) {
+        e = ra::launch_chain_sum(gap_cost, n_gaps, chain_gap_off, chain_gap_cnt, n_chains, out_chain_cost, st);
+        if (e != hipSuccess) return hip_fail(e, "chain sum kernel");
+    }
+    if (n_reads > 0) {
+        e = ra::launch_decide(out_chain_cost, n_chains, cand_off, cand_cnt, chain_events, n_reads, b_match,
+                              threshold, out_best, out_best_score, out_mapped, true, st);
+        if (e != hipSuccess) return hip_fail(e, "decide kernel");
+    }
     return RAWALIGN_OK;
 }
 

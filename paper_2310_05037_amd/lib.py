@@ -32,8 +32,8 @@ FLAG_TIMING = 1
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
     "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
-    "rawalign_decide", "rawalign_map_bnb", "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing",
-    "rawalign_last_error", "rawalign_version",
+    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_global_batch", "rawalign_chain_decide",
+    "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing", "rawalign_last_error", "rawalign_version",
 )
 
 
@@ -84,6 +84,8 @@ def load(path: str = LIB_PATH):
     L.rawalign_decide.argtypes = [vp, i64, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp]
     L.rawalign_map_bnb.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp, i64, f64, f64, i32, i32,
                                    vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+    L.rawalign_dtw_global_batch.argtypes = pair_args + [ctypes.POINTER(Opts)]
+    L.rawalign_chain_decide.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_last_timing.argtypes = [ctypes.POINTER(Timing)]
@@ -122,16 +124,18 @@ def _dev(t, dtype, name):
 
 
 def _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end):
+    """out_end may be None only where the entry point allows it."""
     import torch
     n = q_off.numel()
     for t, nm in ((q_len, "q_len"), (r_off, "r_off"), (r_len, "r_len"), (out_score, "out_score"),
                   (out_end, "out_end")):
-        if t.numel() != n:
+        if t is not None and t.numel() != n:
             raise ValueError(f"{nm} has {t.numel()} elements, expected {n}")
     return [_dev(q, torch.float32, "q"), q.numel(), _dev(q_off, torch.int64, "q_off"),
             _dev(q_len, torch.int32, "q_len"), _dev(r, torch.float32, "r"), r.numel(),
             _dev(r_off, torch.int64, "r_off"), _dev(r_len, torch.int32, "r_len"), n,
-            _dev(out_score, torch.float32, "out_score"), _dev(out_end, torch.int32, "out_end")]
+            _dev(out_score, torch.float32, "out_score"),
+            None if out_end is None else _dev(out_end, torch.int32, "out_end")]
 
 
 def opts_default() -> Opts:
@@ -210,6 +214,33 @@ def rawalign_decide(score, cand_off, cand_cnt, n_events, out_best, out_score, ou
                                   _dev(out_mapped, torch.uint8, "out_mapped"), _stream(stream)))
 
 
+def rawalign_dtw_global_batch(q, q_off, q_len, r, r_off, r_len, out_score, out_end=None, opts=None, stream=None):
+    _check(load().rawalign_dtw_global_batch(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
+                                            _stream(stream), None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_chain_decide(gap_cost, chain_gap_off, chain_gap_cnt, chain_events, cand_off, cand_cnt,
+                          out_chain_cost, out_best, out_best_score, out_mapped, b_match=0.4, threshold=20.0,
+                          stream=None):
+    import torch
+    n_chains = chain_gap_off.numel()
+    n_reads = cand_off.numel()
+    for t, nm, k in ((chain_gap_cnt, "chain_gap_cnt", n_chains), (chain_events, "chain_events", n_chains),
+                     (out_chain_cost, "out_chain_cost", n_chains), (cand_cnt, "cand_cnt", n_reads),
+                     (out_best, "out_best", n_reads), (out_best_score, "out_best_score", n_reads),
+                     (out_mapped, "out_mapped", n_reads)):
+        if t.numel() != k:
+            raise ValueError(f"{nm} has {t.numel()} elements, expected {k}")
+    _check(load().rawalign_chain_decide(
+        _dev(gap_cost, torch.float32, "gap_cost"), gap_cost.numel(),
+        _dev(chain_gap_off, torch.int64, "chain_gap_off"), _dev(chain_gap_cnt, torch.int32, "chain_gap_cnt"),
+        _dev(chain_events, torch.int32, "chain_events"), n_chains,
+        _dev(cand_off, torch.int64, "cand_off"), _dev(cand_cnt, torch.int32, "cand_cnt"), n_reads,
+        float(b_match), float(threshold), _dev(out_chain_cost, torch.float32, "out_chain_cost"),
+        _dev(out_best, torch.int32, "out_best"), _dev(out_best_score, torch.float64, "out_best_score"),
+        _dev(out_mapped, torch.uint8, "out_mapped"), _stream(stream)))
+
+
 def rawalign_autotune(q, q_off, q_len, r, r_off, r_len, out_score, out_end, cache_path=None, stream=None) -> Opts:
     best = Opts()
     _check(load().rawalign_autotune(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
@@ -265,6 +296,46 @@ class DeviceBatch:
         import torch
         torch.cuda.synchronize()
         return self.score.cpu().numpy(), self.end.cpu().numpy()
+
+
+class DeviceAnchored:
+    """A workloads.AnchoredBatch on the device: gap DTW (rawalign_dtw_global_batch)
+    then chain sums and the decision (rawalign_chain_decide)."""
+
+    def __init__(self, ab, device="cuda"):
+        import torch
+
+        def t(x, dt):
+            return torch.from_numpy(np.ascontiguousarray(x).astype(dt)).to(device)
+
+        self.ab = ab
+        self.q = t(ab.q, np.float32)
+        self.r = t(ab.r, np.float32)
+        self.gap_q_off, self.gap_q_len = t(ab.gap_q_off, np.int64), t(ab.gap_q_len, np.int32)
+        self.gap_r_off, self.gap_r_len = t(ab.gap_r_off, np.int64), t(ab.gap_r_len, np.int32)
+        self.chain_gap_off, self.chain_gap_cnt = t(ab.chain_gap_off, np.int64), t(ab.chain_gap_cnt, np.int32)
+        self.chain_events = t(ab.chain_events, np.int32)
+        self.cand_off, self.cand_cnt = t(ab.cand_off, np.int64), t(ab.cand_cnt, np.int32)
+        self.gap_cost = torch.empty(ab.n_gaps, dtype=torch.float32, device=device)
+        self.gap_end = torch.empty(ab.n_gaps, dtype=torch.int32, device=device)
+        self.chain_cost = torch.empty(ab.n_chains, dtype=torch.float32, device=device)
+        n_reads = len(ab.cand_off)
+        self.best = torch.empty(n_reads, dtype=torch.int32, device=device)
+        self.best_score = torch.empty(n_reads, dtype=torch.float64, device=device)
+        self.mapped = torch.empty(n_reads, dtype=torch.uint8, device=device)
+
+    def run(self, opts=None, b_match=0.4, threshold=20.0, stream=None, ends=False):
+        rawalign_dtw_global_batch(self.q, self.gap_q_off, self.gap_q_len, self.r, self.gap_r_off, self.gap_r_len,
+                                  self.gap_cost, self.gap_end if ends else None, opts=opts, stream=stream)
+        rawalign_chain_decide(self.gap_cost, self.chain_gap_off, self.chain_gap_cnt, self.chain_events,
+                              self.cand_off, self.cand_cnt, self.chain_cost, self.best, self.best_score,
+                              self.mapped, b_match=b_match, threshold=threshold, stream=stream)
+
+    def results(self):
+        import torch
+        torch.cuda.synchronize()
+        return (self.gap_cost.cpu().numpy(), self.chain_cost.cpu().numpy(), self.best.cpu().numpy(),
+                self.best_score.cpu().numpy(), self.mapped.cpu().numpy())
 
 
 def dtw(batch, opts=None, plain=False):

@@ -368,6 +368,7 @@ class AnchoredBatch:
     chain_gap_off: np.ndarray  # int64 per chain
     chain_gap_cnt: np.ndarray  # int32 per chain
     chain_events: np.ndarray   # int32 per chain
+    chain_levels: np.ndarray   # int32 per chain: reference levels its anchors span
     cand_off: np.ndarray       # int64 per read
     cand_cnt: np.ndarray       # int32 per read
     true_chain: np.ndarray     # int64 per read
@@ -408,9 +409,9 @@ def _chain_gaps(anchors, ev_at, lv_at):
     but no levels (or levels but no events) has no path between the anchor
     corners; such a gap is merged with the following anchor and gap.
     Returns (list of (q offset, q length, r offset, r length), first event,
-    end event)."""
+    end event, levels spanned)."""
     if not anchors:
-        return [], 0, 0
+        return [], 0, 0, 0
     kept = [anchors[0]]
     for a in anchors[1:]:
         prev_end = kept[-1][1]
@@ -424,7 +425,7 @@ def _chain_gaps(anchors, ev_at, lv_at):
         e0, e1 = ev_at(kept[t][1]), ev_at(kept[t + 1][0])
         l0, l1 = lv_at(kept[t][1]), lv_at(kept[t + 1][0])
         gaps.append((e0, e1 - e0, l0, l1 - l0))
-    return gaps, ev_at(kept[0][0]), ev_at(kept[-1][1])
+    return gaps, ev_at(kept[0][0]), ev_at(kept[-1][1]), lv_at(kept[-1][1]) - lv_at(kept[0][0])
 
 
 def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_index: int = 5) -> AnchoredBatch:
@@ -448,7 +449,7 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
     reads = []
     read_base = []
     g_q_off, g_q_len, g_r_off, g_r_len = [], [], [], []
-    c_gap_off, c_gap_cnt, c_events = [], [], []
+    c_gap_off, c_gap_cnt, c_events, c_levels = [], [], [], []
     cand_cnt, true_chain = [], []
     q_pos = 0
     n_done = 0
@@ -464,7 +465,8 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
         for c in range(k):
             if c == 0:
                 anchors = _anchor_walk(rng, used)
-                gaps, e_first, e_end = _chain_gaps(anchors, lambda u: int(ev_start[u]), lambda u: start + u)
+                gaps, e_first, e_end, levels = _chain_gaps(anchors, lambda u: int(ev_start[u]),
+                                                           lambda u: start + u)
             else:
                 span = max(1, int(len(ev) * rng.uniform(0.2, 1.0)))
                 e0 = int(rng.integers(0, len(ev) - span + 1))
@@ -475,10 +477,11 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
                 d_start = np.concatenate([[0], np.cumsum(dwell)]).astype(np.int64)
                 d_start = np.minimum(d_start, span)
                 anchors = _anchor_walk(rng, kmers)
-                gaps, e_first, e_end = _chain_gaps(anchors, lambda u: e0 + int(d_start[u]), lambda u: l0 + u)
+                gaps, e_first, e_end, levels = _chain_gaps(anchors, lambda u: e0 + int(d_start[u]), lambda u: l0 + u)
             c_gap_off.append(len(g_q_off))
             c_gap_cnt.append(len(gaps))
             c_events.append(e_end - e_first)
+            c_levels.append(levels)
             for (eo, el, lo, ll) in gaps:
                 g_q_off.append(q_pos + eo)
                 g_q_len.append(el)
@@ -494,7 +497,7 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
                          np.array(g_q_off, dtype=np.int64), np.array(g_q_len, dtype=np.int32),
                          np.array(g_r_off, dtype=np.int64), np.array(g_r_len, dtype=np.int32),
                          np.array(c_gap_off, dtype=np.int64), np.array(c_gap_cnt, dtype=np.int32),
-                         np.array(c_events, dtype=np.int32), cand_off, cand_cnt,
+                         np.array(c_events, dtype=np.int32), np.array(c_levels, dtype=np.int32), cand_off, cand_cnt,
                          np.array(true_chain, dtype=np.int64),
                          {"seed_index": seed_index, "reference_bases": ref_bases,
                           "anchor_kmers": list(ANCHOR_KMERS), "gap_mean_kmers": GAP_MEAN_KMERS})

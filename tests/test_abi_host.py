@@ -91,6 +91,27 @@ def test_argument_errors_without_device(L):
     # decide with a negative read count
     rc = so.rawalign_decide(fake, 1, fake, fake, fake, -1, 0.4, 20.0, fake, fake, fake, None)
     assert rc == L.RAWALIGN_EINVAL
+    # global alignment: the end output is optional, the anti-diagonal kernel is not offered
+    rc = so.rawalign_dtw_global_batch(None, 0, None, None, None, 0, None, None, 0, None, None, None, None)
+    assert rc == L.RAWALIGN_OK
+    rc = so.rawalign_dtw_global_batch(fake, 10, fake, fake, fake, 10, fake, fake, -1, fake, None, None, None)
+    assert rc == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_global_batch(fake, 10, fake, fake, fake, 10, fake, fake, 2, None, None, None, None)
+    assert rc == L.RAWALIGN_EINVAL and b"null" in so.rawalign_last_error()
+    o = L.opts_default()
+    o.long_kernel = L.LONG_ANTIDIAG
+    rc = so.rawalign_dtw_global_batch(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, None, None,
+                                      ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
+    # chain sums and decision
+    def chains(n_gaps=4, n_chains=2, n_reads=1, gap_cost=fake, events=fake, threshold=20.0):
+        return so.rawalign_chain_decide(gap_cost, n_gaps, fake, fake, events, n_chains, fake, fake, n_reads, 0.4,
+                                        threshold, fake, fake, fake, fake, None)
+    assert chains(n_chains=-1) == L.RAWALIGN_EINVAL and b"n_chains" in so.rawalign_last_error()
+    assert chains(events=None) == L.RAWALIGN_EINVAL and b"null" in so.rawalign_last_error()
+    assert chains(gap_cost=None) == L.RAWALIGN_EINVAL and b"gap_cost" in so.rawalign_last_error()
+    assert chains(threshold=float("nan")) == L.RAWALIGN_EINVAL
+    assert chains(n_gaps=0, n_chains=0, n_reads=0) == L.RAWALIGN_OK
 
 
 def test_binding_rejects_host_tensors(L):
