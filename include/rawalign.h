@@ -230,10 +230,12 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
  *   out_end    device int32 per pair, may be NULL: m-1 (-1 for the
  *              degenerate pairs below)
  *   opts       mode and streams as in rawalign_dtw_batch_ex; long_kernel must
- *              be RAWALIGN_LONG_STRIPED; NULL = defaults (not the tuned
- *              settings)
+ *              be RAWALIGN_LONG_STRIPED; NULL = library defaults with three
+ *              streams (not the tuned settings)
  * Pairs of at most 64 levels are aligned one pair per lane (grouped on the
- * device by width and query length); wider ones by the striped kernels.
+ * device into 8 width classes, longest queries first); wider ones by the
+ * striped kernels.  With three streams the width classes and the striped
+ * kernels run concurrently on internal streams joined back to `stream`.
  * Degenerate pairs: n == m == 0 (the anchors touch diagonally) costs 0;
  * n == 0 or m == 0 alone costs +inf (no path through the gap's own cells).
  * Invalid slices get NaN (end -2), as in rawalign_dtw_batch.  Scratch as in

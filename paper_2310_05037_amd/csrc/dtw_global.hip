@@ -48,13 +48,26 @@ __global__ void k_tiny_zero(TinyScratch t) {
     }
 }
 
-// Per-workgroup histogram in LDS, one global atomic per non-empty bin.
+// Workgroups take contiguous ranges of pairs (at most kTinyPlanGrid
+// workgroups), count them per bin in LDS and add each non-empty bin to the
+// global histogram once: a million gaps fall into a few dozen busy bins,
+// and one global atomic per bin per workgroup keeps those bins uncontended.
+constexpr int kTinyPlanGrid = 512;
+
+RA_DEV void tiny_range(int64_t n_pairs, int64_t &lo, int64_t &hi) {
+    const int64_t per = ((n_pairs + gridDim.x - 1) / gridDim.x + kTinyPlanBlock - 1) / kTinyPlanBlock * kTinyPlanBlock;
+    lo = (int64_t)blockIdx.x * per;
+    hi = lo + per < n_pairs ? lo + per : n_pairs;
+}
+
 __global__ __launch_bounds__(kTinyPlanBlock) void k_tiny_count(PairArrays a, int64_t n_pairs, TinyScratch t) {
     __shared__ int h[kTinyBins];
     for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock) h[i] = 0;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n_pairs && tiny_pair(a, p)) atomicAdd(&h[tiny_bin(a.q_len[p], a.r_len[p])], 1);
+    int64_t lo, hi;
+    tiny_range(n_pairs, lo, hi);
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kTinyPlanBlock)
+        if (tiny_pair(a, p)) atomicAdd(&h[tiny_bin(a.q_len[p], a.r_len[p])], 1);
     __syncthreads();
     for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock)
         if (h[i]) atomicAdd(&t.hist[i], h[i]);
@@ -84,24 +97,30 @@ __global__ __launch_bounds__(kTinyBins) void k_tiny_scan(TinyScratch t) {
     }
 }
 
-// Each workgroup ranks its gaps per bin in LDS and reserves one contiguous
-// range per bin with a single global atomic on the bin's cursor.
+// Each workgroup counts its range per bin in LDS, reserves one contiguous
+// slot range per bin with a single global atomic on the bin's cursor, then
+// ranks its pairs in LDS again and writes them there.
 __global__ __launch_bounds__(kTinyPlanBlock) void k_tiny_scatter(PairArrays a, int64_t n_pairs, TinyScratch t) {
     __shared__ int cnt[kTinyBins];
     __shared__ int base[kTinyBins];
     for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock) cnt[i] = 0;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int bin = -1, rank = 0;
-    if (p < n_pairs && tiny_pair(a, p)) {
-        bin = tiny_bin(a.q_len[p], a.r_len[p]);
-        rank = atomicAdd(&cnt[bin], 1);
+    int64_t lo, hi;
+    tiny_range(n_pairs, lo, hi);
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kTinyPlanBlock)
+        if (tiny_pair(a, p)) atomicAdd(&cnt[tiny_bin(a.q_len[p], a.r_len[p])], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock) {
+        if (cnt[i]) base[i] = atomicAdd(&t.hist[i], cnt[i]);
+        cnt[i] = 0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kTinyBins; i += kTinyPlanBlock)
-        if (cnt[i]) base[i] = atomicAdd(&t.hist[i], cnt[i]);
-    __syncthreads();
-    if (bin >= 0) t.list[base[bin] + rank] = (int32_t)p;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kTinyPlanBlock) {
+        if (tiny_pair(a, p)) {
+            const int bin = tiny_bin(a.q_len[p], a.r_len[p]);
+            t.list[base[bin] + atomicAdd(&cnt[bin], 1)] = (int32_t)p;
+        }
+    }
 }
 
 // One query row over the lane's W slots.  diag0: north-west value of slot 0
@@ -111,6 +130,16 @@ RA_DEV void tiny_row(float qv, float diag0, const float (&rv)[W], const float (&
     An[0] = fabsf(qv - rv[0]) + fminf(diag0, Ao[0]);
 #pragma unroll
     for (int v = 1; v < W; ++v) An[v] = cell(qv, rv[v], Ao[v - 1], Ao[v], An[v - 1]);
+}
+
+// Query events are read kTinyQB rows at a time, one block ahead of use, so
+// the per-lane gathers are in flight while the previous block computes.
+constexpr int kTinyQB = 8;
+
+template <int W>
+RA_DEV void tiny_qblock(const float *qp, int n, int i0, float (&qb)[kTinyQB]) {
+#pragma unroll
+    for (int k = 0; k < kTinyQB; ++k) qb[k] = qp[i0 + k < n ? i0 + k : n - 1];
 }
 
 // Gaps of width class `cls` (m <= W levels), 64 per wave, in list order.
@@ -141,16 +170,20 @@ __global__ __launch_bounds__(64) void k_tiny(PairArrays a, TinyScratch t, int cl
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
         float res = kInf;
-        float qa = qp[0];
-        for (int i = 0; i < nmax; i += 2) {
-            const float q0 = qa;
-            const float q1 = qp[i + 1 < n ? i + 1 : n - 1];
-            qa = qp[i + 2 < n ? i + 2 : n - 1];
-            tiny_row<W>(q0, corner, rv, A, B);
-            corner = kInf;
-            if (i == n - 1) res = B[W - 1];
-            tiny_row<W>(q1, kInf, rv, B, A);
-            if (i + 1 == n - 1) res = A[W - 1];
+        float qc[kTinyQB], qn[kTinyQB];
+        tiny_qblock<W>(qp, n, 0, qc);
+        for (int i0 = 0; i0 < nmax; i0 += kTinyQB) {
+            tiny_qblock<W>(qp, n, i0 + kTinyQB, qn);
+#pragma unroll
+            for (int k = 0; k < kTinyQB; k += 2) {
+                tiny_row<W>(qc[k], corner, rv, A, B);
+                corner = kInf;
+                if (i0 + k == n - 1) res = B[W - 1];
+                tiny_row<W>(qc[k + 1], kInf, rv, B, A);
+                if (i0 + k + 1 == n - 1) res = A[W - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < kTinyQB; ++k) qc[k] = qn[k];
         }
         if (act) {
             a.out_score[p] = res;
@@ -171,26 +204,31 @@ static int tiny_occupancy() {
 }
 
 template <int C>
-static hipError_t launch_tiny_class(const PairArrays &a, const TinyScratch &t, int cus, hipStream_t stream) {
+static hipError_t launch_tiny_class(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
     if constexpr (C < kTinyClasses) {
         const unsigned grid = (unsigned)(cus * tiny_occupancy<C>());
-        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, stream, a, t, C);
+        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[C % 3], a, t, C);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_tiny_class<C + 1>(a, t, cus, stream);
+        return launch_tiny_class<C + 1>(a, t, cus, st);
     }
     return hipSuccess;
 }
 
-hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus, hipStream_t stream) {
+hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, hipStream_t stream) {
     hipLaunchKernelGGL(k_tiny_zero, dim3((kTinyBins + 255) / 256), dim3(256), 0, stream, t);
-    const unsigned g = (unsigned)((n_pairs + kTinyPlanBlock - 1) / kTinyPlanBlock);
+    int64_t g64 = (n_pairs + kTinyPlanBlock - 1) / kTinyPlanBlock;
+    const unsigned g = (unsigned)(g64 < kTinyPlanGrid ? g64 : kTinyPlanGrid);
     hipLaunchKernelGGL(k_tiny_count, dim3(g), dim3(kTinyPlanBlock), 0, stream, a, n_pairs, t);
     hipLaunchKernelGGL(k_tiny_scan, dim3(1), dim3(kTinyBins), 0, stream, t);
     hipLaunchKernelGGL(k_tiny_scatter, dim3(g), dim3(kTinyPlanBlock), 0, stream, a, n_pairs, t);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_tiny_class<0>(a, t, cus, stream);
+    return hipGetLastError();
+}
+
+// Width class c runs on st[c % 3]: each class is about one round of waves,
+// whose time its longest gaps set, so classes on different streams overlap.
+hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
+    return launch_tiny_class<0>(a, t, cus, st);
 }
 
 // ---- chain sums ------------------------------------------------------------------

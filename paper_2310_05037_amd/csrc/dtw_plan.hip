@@ -77,16 +77,28 @@ __global__ void k_plan_zero(PlanScratch s) {
 
 constexpr int kPlanBlock = 256;
 constexpr int kBins = kNumRoutes * kBuckets;
+// Workgroups take contiguous ranges of pairs; at most kPlanGrid of them, so
+// a batch of millions of pairs still adds each busy bin to the global
+// histogram only a few hundred times.
+constexpr int kPlanGrid = 512;
+
+RA_DEV void plan_range(int64_t n_pairs, int64_t &lo, int64_t &hi) {
+    const int64_t per = ((n_pairs + gridDim.x - 1) / gridDim.x + kPlanBlock - 1) / kPlanBlock * kPlanBlock;
+    lo = (int64_t)blockIdx.x * per;
+    hi = lo + per < n_pairs ? lo + per : n_pairs;
+}
 
 // Each workgroup counts its pairs per (route, bucket) in LDS and adds the
 // non-zero bins to the global histogram: one global atomic per bin per
-// workgroup instead of one per pair.
+// workgroup instead of one per pair.  Pairs that need no kernel get their
+// result here.
 __global__ __launch_bounds__(kPlanBlock) void k_plan_count(PlanArgs pa) {
     __shared__ int h[kBins];
     for (int i = threadIdx.x; i < kBins; i += kPlanBlock) h[i] = 0;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < pa.n_pairs) {
+    int64_t lo, hi;
+    plan_range(pa.n_pairs, lo, hi);
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kPlanBlock) {
         int b = 0, e = 0;
         float sc = 0.0f;
         const int route = classify(pa, p, b, sc, e);
@@ -116,31 +128,39 @@ __global__ void k_plan_scan(PlanScratch s) {
     s.queue[route] = 0;
 }
 
-// Each workgroup ranks its pairs per bin in LDS, reserves one contiguous
-// range per bin with a single global atomic on the bin's cursor, and writes
-// its pairs there (in plain mode, one bin per route: workgroups keep their
-// order of arrival at the cursor, pairs inside a workgroup their LDS rank).
+// Each workgroup counts its range per bin in LDS, reserves one contiguous
+// range per bin with a single global atomic on the bin's cursor, then ranks
+// its pairs in LDS again and writes them there (in plain mode, one bin per
+// route: workgroups keep their order of arrival at the cursor, pairs inside
+// a workgroup their LDS rank).
 __global__ __launch_bounds__(kPlanBlock) void k_plan_scatter(PlanArgs pa) {
     __shared__ int cnt[kBins];
     __shared__ int base[kBins];
     for (int i = threadIdx.x; i < kBins; i += kPlanBlock) cnt[i] = 0;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int bin = -1, rank = 0, route = -1;
-    if (p < pa.n_pairs) {
+    int64_t lo, hi;
+    plan_range(pa.n_pairs, lo, hi);
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kPlanBlock) {
         int b = 0, e = 0;
         float sc = 0.0f;
-        route = classify(pa, p, b, sc, e);
-        if (route >= 0) {
-            bin = route * kBuckets + b;
-            rank = atomicAdd(&cnt[bin], 1);
-        }
+        const int route = classify(pa, p, b, sc, e);
+        if (route >= 0) atomicAdd(&cnt[route * kBuckets + b], 1);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kBins; i += kPlanBlock)
+    for (int i = threadIdx.x; i < kBins; i += kPlanBlock) {
         if (cnt[i]) base[i] = atomicAdd(&pa.s.hist[i], cnt[i]);
+        cnt[i] = 0;
+    }
     __syncthreads();
-    if (bin >= 0) pa.s.list[route * pa.s.capacity + base[bin] + rank] = (int32_t)p;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kPlanBlock) {
+        int b = 0, e = 0;
+        float sc = 0.0f;
+        const int route = classify(pa, p, b, sc, e);
+        if (route >= 0) {
+            const int bin = route * kBuckets + b;
+            pa.s.list[route * pa.s.capacity + base[bin] + atomicAdd(&cnt[bin], 1)] = (int32_t)p;
+        }
+    }
 }
 
 hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
@@ -152,7 +172,8 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
     pa.extend = a.rows != nullptr;
     pa.s = s;
     hipLaunchKernelGGL(k_plan_zero, dim3((kBins + 255) / 256), dim3(256), 0, stream, s);
-    const unsigned g = (unsigned)((n_pairs + kPlanBlock - 1) / kPlanBlock);
+    const int64_t g64 = (n_pairs + kPlanBlock - 1) / kPlanBlock;
+    const unsigned g = (unsigned)(g64 < kPlanGrid ? g64 : kPlanGrid);
     hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(kPlanBlock), 0, stream, pa);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
     hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(kPlanBlock), 0, stream, pa);

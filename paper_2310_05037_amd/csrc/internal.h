@@ -157,7 +157,8 @@ hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *can
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
                          int32_t *out_best, double *out_score, uint8_t *out_mapped, bool per_candidate,
                          hipStream_t stream);
-hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus, hipStream_t stream);
+hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, hipStream_t stream);
+hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *streams);
 hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
                             const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
                             hipStream_t stream);

@@ -343,8 +343,8 @@ int run(const Call &c, const rawalign_opts &o) {
     e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "plan kernels");
     if (c.global) {
-        e = ra::launch_tiny(a, c.n_pairs, tiny_view(*s), info.cus, c.stream);
-        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
+        e = ra::launch_tiny_plan(a, c.n_pairs, tiny_view(*s), c.stream);
+        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane planning");
     }
     if (timing) (void)hipEventRecord(s->ev[1], c.stream);
     hipStream_t st[3] = {c.stream, c.stream, c.stream};
@@ -354,6 +354,10 @@ int run(const Call &c, const rawalign_opts &o) {
             st[i] = s->sub[i];
             if ((e = hipStreamWaitEvent(st[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
+    }
+    if (c.global) {
+        e = ra::launch_tiny(a, tiny_view(*s), info.cus, st);
+        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
     }
     // Longest regions first: they bound the makespan.
     typedef hipError_t (*Launch)(const ra::PairArrays &, int64_t, const ra::LaunchCfg &, const ra::PlanScratch &,
@@ -616,6 +620,7 @@ int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_o
                               const rawalign_opts *opts) {
     rawalign_opts o;
     defaults(o);
+    o.streams = 3;   // the width classes of the one-gap-per-lane kernel overlap
     if (opts) o = *opts;
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
            nullptr, 0, nullptr, nullptr, (hipStream_t)stream, true};
