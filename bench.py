@@ -194,7 +194,7 @@ def bnb_leg(lib, b, opts, steps: int = 3, block_rows: int = 512):
             "entry_point": "rawalign_map_bnb"}
 
 
-def anchored_leg(lib, steps: int = 10, warmup: int = 2):
+def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
     """Anchor-guided alignment (Sec. 2.4.2) of 100,000 candidate chains of
     reads shaped like the uneven batch: global DTW of every gap between
     anchors (one gap per lane up to 64 levels, striped kernels above), chain
@@ -220,7 +220,10 @@ def anchored_leg(lib, steps: int = 10, warmup: int = 2):
     _, _, best, _, mapped = da.results()
     span_cells = int(np.dot(ab.chain_events.astype(np.int64), ab.chain_levels.astype(np.int64)))
     tiny = ab.gap_r_len <= 64
+    ops = VALU_OPS_PER_CELL * ab.cells / (dev_ms / 1e3)
     return {"ms_per_batch": dt * 1e3, "device_ms_per_batch": dev_ms, "chains": ab.n_chains, "gaps": ab.n_gaps,
+            "roofline": {"bound": "alu", "achieved": ops / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
+                         "frac": ops / valu_peak, "over": "whole call: planning, gap kernels, chain sums, decision"},
             "gaps_one_per_lane": int(tiny.sum()), "gap_cells": ab.cells,
             "gap_gcups": ab.cells / (dev_ms / 1e3) / 1e9, "chains_per_s": ab.n_chains / (dev_ms / 1e3),
             "chain_span_cells": span_cells,
@@ -238,6 +241,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="time only the tuned path (for profiling runs)")
     ap.add_argument("--skip-anchored", action="store_true", help="leave out the anchor-guided alignment leg")
+    ap.add_argument("--only-anchored", action="store_true",
+                    help="run only the anchor-guided alignment leg and print its JSON (for profiling runs)")
     ap.add_argument("--opts", type=str, default="", help="JSON dict of rawalign_opts fields for the tuned path")
     ap.add_argument("--no-autotune", action="store_true", help="time the library defaults instead of tuned settings")
     ap.add_argument("--serving-reads", type=int, default=20000, help="reads in the serving leg (0: skip it)")
@@ -264,6 +269,9 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     cus = props.multi_processor_count
     valu_peak = cus * LANES_PER_CU * CLOCK_HZ
+    if args.only_anchored:
+        print(json.dumps({"anchored": anchored_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
 
     b = workloads.uneven_batch()
     cells = b.cells
@@ -318,7 +326,7 @@ def main():
     if not args.skip_plain:
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
     if not args.skip_anchored:
-        variants["anchored"] = anchored_leg(lib)
+        variants["anchored"] = anchored_leg(lib, valu_peak)
 
     # dominant kernel: the route with the largest average duration
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}

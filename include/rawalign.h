@@ -229,9 +229,10 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
  *   out_score  device float32 per pair: D(n-1, m-1)
  *   out_end    device int32 per pair, may be NULL: m-1 (-1 for the
  *              degenerate pairs below)
- *   opts       mode and streams as in rawalign_dtw_batch_ex; long_kernel must
- *              be RAWALIGN_LONG_STRIPED; NULL = library defaults with three
- *              streams (not the tuned settings)
+ *   opts       mode, streams and grids as in rawalign_dtw_batch_ex;
+ *              long_kernel must be RAWALIGN_LONG_STRIPED; NULL = defaults
+ *              for anchor gaps: three streams, one persistent wave per CU
+ *              for regions above 2048 levels (not the tuned settings)
  * Pairs of at most 64 levels are aligned one pair per lane (grouped on the
  * device into 8 width classes, longest queries first); wider ones by the
  * striped kernels.  With three streams the width classes and the striped

@@ -203,14 +203,15 @@ static int tiny_occupancy() {
     return occ;
 }
 
+// Widest class first: its longest gaps are the longest serial chains.
 template <int C>
 static hipError_t launch_tiny_class(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
-    if constexpr (C < kTinyClasses) {
+    if constexpr (C >= 0) {
         const unsigned grid = (unsigned)(cus * tiny_occupancy<C>());
-        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[C % 3], a, t, C);
+        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[(kTinyClasses - 1 - C) % 3], a, t, C);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_tiny_class<C + 1>(a, t, cus, st);
+        return launch_tiny_class<C - 1>(a, t, cus, st);
     }
     return hipSuccess;
 }
@@ -225,10 +226,11 @@ hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScra
     return hipGetLastError();
 }
 
-// Width class c runs on st[c % 3]: each class is about one round of waves,
-// whose time its longest gaps set, so classes on different streams overlap.
+// The width classes go round the three streams, widest first: each class is
+// about one round of waves, whose time its longest gaps set, so classes on
+// different streams overlap.
 hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
-    return launch_tiny_class<0>(a, t, cus, st);
+    return launch_tiny_class<kTinyClasses - 1>(a, t, cus, st);
 }
 
 // ---- chain sums ------------------------------------------------------------------

@@ -620,7 +620,13 @@ int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_o
                               const rawalign_opts *opts) {
     rawalign_opts o;
     defaults(o);
-    o.streams = 3;   // the width classes of the one-gap-per-lane kernel overlap
+    // Defaults for anchor gaps: the width classes of the one-gap-per-lane
+    // kernel overlap on three streams, and the routes above 2048 levels,
+    // which such gaps hardly reach, get one persistent wave per CU instead
+    // of a full grid that would mostly just start and exit.
+    o.streams = 3;
+    o.hi_waves_per_cu = 1;
+    o.long_waves_per_cu = 1;
     if (opts) o = *opts;
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
            nullptr, 0, nullptr, nullptr, (hipStream_t)stream, true};
