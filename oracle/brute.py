@@ -97,3 +97,34 @@ def brute_global_dtw(q, r):
         if i + 1 < n and j + 1 < m:
             stack.append((i + 1, j + 1, acc + abs(q[i + 1] - r[j + 1])))
     return best, count
+
+
+def brute_span(q, r):
+    """(cost, end, start) by explicit enumeration of subsequence paths (as
+    brute_dtw): the cheapest cost, the smallest final column among the
+    cheapest paths, and among the cheapest paths ending there the largest
+    first column.  Empty query: (0, -1, -1); empty region: (+inf, -1, -1)."""
+    q = [float(x) for x in q]
+    r = [float(x) for x in r]
+    n, m = len(q), len(r)
+    if n == 0:
+        return 0.0, -1, -1
+    if m == 0:
+        return math.inf, -1, -1
+    best = {}   # end column -> (cost, largest start among that cost)
+    stack = [(0, j0, j0, abs(q[0] - r[j0])) for j0 in range(m)]
+    while stack:
+        i, j, s0, acc = stack.pop()
+        if i == n - 1:
+            c, st = best.get(j, (math.inf, -1))
+            if acc < c or (acc == c and s0 > st):
+                best[j] = (acc, s0)
+        if i + 1 < n:
+            stack.append((i + 1, j, s0, acc + abs(q[i + 1] - r[j])))
+        if j + 1 < m:
+            stack.append((i, j + 1, s0, acc + abs(q[i] - r[j + 1])))
+        if i + 1 < n and j + 1 < m:
+            stack.append((i + 1, j + 1, s0, acc + abs(q[i + 1] - r[j + 1])))
+    cost = min(c for c, _ in best.values())
+    end = min(j for j, (c, _) in best.items() if c == cost)
+    return cost, end, best[end][1]

@@ -280,6 +280,126 @@ float oracle_dtw_global_f32(const float *q, int64_t n, const float *r, int64_t m
     return g;
 }
 
+/*
+ * Start of the alignment.  The paper's DTW reports a score by default and
+ * can add the alignment path to its output (Sec. 2.4); the path's first
+ * region column is its start.  Given the end column e of the subsequence
+ * recurrence above, the read is aligned backwards: the reversed query
+ * q_{n-1} .. q_0 against the reversed region prefix r_e .. r_0, the path
+ * anchored at its first cell (the forward cell (n-1, e)) and free to finish
+ * anywhere in the last reversed row (forward row 0):
+ *
+ *   R(-1,-1) = 0,  R(-1,k) = +inf (k >= 0),  R(i,-1) = +inf (i >= 0)
+ *   R(i,k)   = |q_{n-1-i} - r_{e-k}| + min{ R(i-1,k-1), R(i-1,k), R(i,k-1) }
+ *   k*       = smallest k minimising R(n-1, k),   start = e - k*
+ *
+ * A reversed path is a forward path read backwards, so min_k R(n-1, k) is
+ * C_DTW in exact arithmetic, and k* picks the largest first column among
+ * the optimal paths that end at e: the shortest optimal alignment.  The
+ * same steps in float give the float start.
+ *
+ * Degenerate pairs: end -1 (empty query or region) gives start -1.
+ */
+static int32_t rev_argmin_f64(const float *q, int64_t n, const float *r, int32_t e)
+{
+    int64_t m = (int64_t)e + 1;
+    double *prev = malloc((size_t)(m + 1) * sizeof(double));
+    double *cur = malloc((size_t)(m + 1) * sizeof(double));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return -2;
+    }
+    prev[0] = 0.0; /* R(-1,-1): the anchored first cell */
+    for (int64_t k = 0; k < m; ++k)
+        prev[k + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        double qi = (double)q[n - 1 - i];
+        for (int64_t k = 0; k < m; ++k) {
+            double c = fabs(qi - (double)r[e - k]);
+            cur[k + 1] = c + min3_d(prev[k], prev[k + 1], cur[k]);
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    int32_t arg = 0;
+    double best = prev[1];
+    for (int64_t k = 1; k < m; ++k) {
+        if (prev[k + 1] < best) {
+            best = prev[k + 1];
+            arg = (int32_t)k;
+        }
+    }
+    free(prev);
+    free(cur);
+    return arg;
+}
+
+static int32_t rev_argmin_f32(const float *q, int64_t n, const float *r, int32_t e)
+{
+    int64_t m = (int64_t)e + 1;
+    float *prev = malloc((size_t)(m + 1) * sizeof(float));
+    float *cur = malloc((size_t)(m + 1) * sizeof(float));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        return -2;
+    }
+    prev[0] = 0.0f;
+    for (int64_t k = 0; k < m; ++k)
+        prev[k + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        float qi = q[n - 1 - i];
+        for (int64_t k = 0; k < m; ++k) {
+            float d = qi - r[e - k];
+            float c = fabsf(d);
+            cur[k + 1] = c + min3_f(prev[k], prev[k + 1], cur[k]);
+        }
+        float *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    int32_t arg = 0;
+    float best = prev[1];
+    for (int64_t k = 1; k < m; ++k) {
+        if (prev[k + 1] < best) {
+            best = prev[k + 1];
+            arg = (int32_t)k;
+        }
+    }
+    free(prev);
+    free(cur);
+    return arg;
+}
+
+/* Subsequence DTW with its start: returns C_DTW, writes end and start. */
+double oracle_dtw_span_f64(const float *q, int64_t n, const float *r, int64_t m, int32_t *end, int32_t *start)
+{
+    double c = oracle_dtw_f64(q, n, r, m, NULL, NULL, end);
+    if (*end < 0) {
+        *start = *end;
+        return c;
+    }
+    int32_t k = rev_argmin_f64(q, n, r, *end);
+    *start = k < 0 ? k : *end - k;
+    return c;
+}
+
+float oracle_dtw_span_f32(const float *q, int64_t n, const float *r, int64_t m, int32_t *end, int32_t *start)
+{
+    float c = oracle_dtw_f32(q, n, r, m, NULL, NULL, end);
+    if (*end < 0) {
+        *start = *end;
+        return c;
+    }
+    int32_t k = rev_argmin_f32(q, n, r, *end);
+    *start = k < 0 ? k : *end - k;
+    return c;
+}
+
 /* ---- batches: pairs are independent, threads take pairs from a counter ---- */
 
 struct batch_job {
@@ -294,6 +414,7 @@ struct batch_job {
     float *out32;
     int32_t *out_end;   /* NULL for global alignment (no end column) */
     int global;
+    int32_t *out_start; /* span: start column per pair */
     int64_t next;
 };
 
@@ -306,7 +427,14 @@ static void *batch_worker(void *arg)
             break;
         const float *qp = job->q + job->q_off[p];
         const float *rp = job->r + job->r_off[p];
-        if (job->global) {
+        if (job->out_start) {
+            if (job->out64)
+                job->out64[p] = oracle_dtw_span_f64(qp, job->q_len[p], rp, job->r_len[p], &job->out_end[p],
+                                                    &job->out_start[p]);
+            else
+                job->out32[p] = oracle_dtw_span_f32(qp, job->q_len[p], rp, job->r_len[p], &job->out_end[p],
+                                                    &job->out_start[p]);
+        } else if (job->global) {
             if (job->out64)
                 job->out64[p] = oracle_dtw_global_f64(qp, job->q_len[p], rp, job->r_len[p]);
             else
@@ -350,7 +478,7 @@ int oracle_dtw_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, out_end, 0, 0};
+                            out_score, NULL, out_end, 0, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -360,7 +488,7 @@ int oracle_dtw_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, out_end, 0, 0};
+                            NULL, out_score, out_end, 0, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -370,7 +498,7 @@ int oracle_dtw_global_batch_f64(const float *q, const int64_t *q_off, const int3
                                 int64_t n_pairs, double *out_score, int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, NULL, 1, 0};
+                            out_score, NULL, NULL, 1, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -379,6 +507,27 @@ int oracle_dtw_global_batch_f32(const float *q, const int64_t *q_off, const int3
                                 int64_t n_pairs, float *out_score, int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, NULL, 1, 0};
+                            NULL, out_score, NULL, 1, NULL, 0};
+    return run_batch(&job, n_threads);
+}
+
+/* Subsequence DTW with start and end of every pair. */
+int oracle_dtw_span_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, const int64_t *r_off, const int32_t *r_len,
+                              int64_t n_pairs, double *out_score, int32_t *out_end, int32_t *out_start,
+                              int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            out_score, NULL, out_end, 0, out_start, 0};
+    return run_batch(&job, n_threads);
+}
+
+int oracle_dtw_span_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, const int64_t *r_off, const int32_t *r_len,
+                              int64_t n_pairs, float *out_score, int32_t *out_end, int32_t *out_start,
+                              int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            NULL, out_score, out_end, 0, out_start, 0};
     return run_batch(&job, n_threads);
 }

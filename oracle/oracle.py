@@ -11,6 +11,11 @@ with the HIP library.
 * ``decide``: the mapping decision of Sec. 2.3: Score = B_Match * N_Read -
   C_DTW per candidate, the highest score of a read is mapped iff it is at
   least Score_Threshold (defaults 0.4 and 20 from Sec. 3.1.5).
+* ``dtw_span_*``: subsequence DTW with the start of the alignment (the
+  path's first region column; Sec. 2.4 lets the path be added to the
+  output): the read aligned backwards against the region prefix ending at
+  the end column, anchored there, free to finish anywhere; ties give the
+  largest start (the shortest optimal alignment).
 * ``dtw_global_*`` / ``chain_costs`` / ``decide_chains``: anchor-guided
   alignment of Sec. 2.4.2: every gap between two consecutive anchors of a
   chain is aligned by global DTW entered and left through the anchor corners;
@@ -67,6 +72,14 @@ def lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, i32p, ctypes.c_int]
+        L.oracle_dtw_span_f64.restype = ctypes.c_double
+        L.oracle_dtw_span_f64.argtypes = [f32p, i64, f32p, i64, i32p, i32p]
+        L.oracle_dtw_span_f32.restype = ctypes.c_float
+        L.oracle_dtw_span_f32.argtypes = [f32p, i64, f32p, i64, i32p, i32p]
+        for name, outp in (("oracle_dtw_span_batch_f64", f64p), ("oracle_dtw_span_batch_f32", f32p)):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, i32p, i32p, ctypes.c_int]
         L.oracle_dtw_global_f64.restype = ctypes.c_double
         L.oracle_dtw_global_f64.argtypes = [f32p, i64, f32p, i64]
         L.oracle_dtw_global_f32.restype = ctypes.c_float
@@ -284,3 +297,59 @@ def decide_chains(chain_cost, chain_events, cand_off, cand_cnt, b_match=B_MATCH,
         if best[k] >= 0 and best_score[k] >= threshold:
             mapped[k] = 1
     return best, best_score, mapped
+
+
+# ---- start of the alignment ------------------------------------------------------
+
+def dtw_span_f64(q, r):
+    """(C_DTW, end, start) in double precision; start -1 with end -1."""
+    q = _f32(q)
+    r = _f32(r)
+    e, st = ctypes.c_int32(0), ctypes.c_int32(0)
+    c = lib().oracle_dtw_span_f64(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r),
+                                  ctypes.byref(e), ctypes.byref(st))
+    return c, e.value, st.value
+
+
+def dtw_span_f32(q, r):
+    """The same with every value in float."""
+    q = _f32(q)
+    r = _f32(r)
+    e, st = ctypes.c_int32(0), ctypes.c_int32(0)
+    c = lib().oracle_dtw_span_f32(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r),
+                                  ctypes.byref(e), ctypes.byref(st))
+    return np.float32(c), e.value, st.value
+
+
+def _span_batch(fn, dtype, q, q_off, q_len, r, r_off, r_len, threads):
+    q = _f32(q)
+    r = _f32(r)
+    q_off = np.ascontiguousarray(q_off, dtype=np.int64)
+    r_off = np.ascontiguousarray(r_off, dtype=np.int64)
+    q_len = np.ascontiguousarray(q_len, dtype=np.int32)
+    r_len = np.ascontiguousarray(r_len, dtype=np.int32)
+    n = len(q_off)
+    assert len(q_len) == n and len(r_off) == n and len(r_len) == n
+    assert n == 0 or (int((q_off + q_len).max()) <= len(q) and int(q_off.min()) >= 0)
+    assert n == 0 or (int((r_off + r_len).max()) <= len(r) and int(r_off.min()) >= 0)
+    score = np.empty(n, dtype=dtype)
+    end = np.empty(n, dtype=np.int32)
+    start = np.empty(n, dtype=np.int32)
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    if n:
+        ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+        fn(_ptr(q, ctypes.c_float), _ptr(q_off, ctypes.c_int64), _ptr(q_len, ctypes.c_int32),
+           _ptr(r, ctypes.c_float), _ptr(r_off, ctypes.c_int64), _ptr(r_len, ctypes.c_int32),
+           n, _ptr(score, ct), _ptr(end, ctypes.c_int32), _ptr(start, ctypes.c_int32), int(threads))
+    return score, end, start
+
+
+def dtw_span_batch_f64(q, q_off, q_len, r, r_off, r_len, threads=None):
+    """(scores f64, ends, starts) of every pair."""
+    return _span_batch(lib().oracle_dtw_span_batch_f64, np.float64, q, q_off, q_len, r, r_off, r_len, threads)
+
+
+def dtw_span_batch_f32(q, q_off, q_len, r, r_off, r_len, threads=None):
+    """(scores f32, ends, starts) of every pair with float arithmetic."""
+    return _span_batch(lib().oracle_dtw_span_batch_f32, np.float32, q, q_off, q_len, r, r_off, r_len, threads)
