@@ -194,6 +194,33 @@ def bnb_leg(lib, b, opts, steps: int = 3, block_rows: int = 512):
             "entry_point": "rawalign_map_bnb"}
 
 
+def span_leg(lib, db, opts, steps: int = 3):
+    """Scores, ends and starts of the same batch (rawalign_dtw_span: the
+    forward pass, then the reversed query against each region prefix up to
+    its end): time per batch, and the cells of the reverse pass."""
+    import torch
+    n = db.batch.n_pairs
+    start = torch.empty(n, dtype=torch.int32, device=db.q.device)
+
+    def once():
+        lib.rawalign_dtw_span(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, db.score, db.end, start,
+                              opts=opts)
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    end = db.end.cpu().numpy().astype(np.int64)
+    st = start.cpu().numpy()
+    rev_cells = int(np.dot(db.batch.q_len.astype(np.int64), np.maximum(end + 1, 0)))
+    fwd = db.batch.cells
+    return {"ms_per_batch": dt * 1e3, "forward_cells": fwd, "reverse_cells": rev_cells,
+            "gcups_both_passes": (fwd + rev_cells) / dt / 1e9, "unit": "GCUPS",
+            "mean_span_levels": float(np.mean(end - st + 1)), "entry_point": "rawalign_dtw_span"}
+
+
 def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
     """Anchor-guided alignment (Sec. 2.4.2) of 100,000 candidate chains of
     reads shaped like the uneven batch: global DTW of every gap between
@@ -325,6 +352,7 @@ def main():
 
     if not args.skip_plain:
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
+        variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
     if not args.skip_anchored:
         variants["anchored"] = anchored_leg(lib, valu_peak)
 

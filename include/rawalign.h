@@ -219,6 +219,31 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
                      uint8_t *out_mapped, void *stream, const rawalign_opts *opts);
 
 /*
+ * Subsequence DTW with the start of each alignment.  The paper reports
+ * scores by default and can add the alignment path to its output (Sec.
+ * 2.4); its first region column is the start.  Two passes over the batch:
+ *   1. rawalign_dtw_batch_ex gives out_score (C_DTW) and out_end (e);
+ *   2. the reversed query q_{n-1} .. q_0 is aligned against the reversed
+ *      region prefix r_e .. r_0, the path anchored at its first cell (the
+ *      forward cell (n-1, e)) and free to finish anywhere in the last
+ *      reversed row; its best end k (smallest on ties) gives
+ *      out_start = e - k.
+ * In exact arithmetic this is the largest first column among the optimal
+ * paths that end at e (the shortest optimal alignment), and the region
+ * interval [start, end] aligned globally costs C_DTW.
+ *   Arguments as in rawalign_dtw_batch_ex, plus out_start (device, int32 per
+ *   pair).  Pairs without an end keep its sentinel as their start (-1
+ *   degenerate, -2 invalid).  opts: as in rawalign_dtw_batch_ex (NULL = tuned
+ *   or defaults) for both passes; long_kernel must be RAWALIGN_LONG_STRIPED.
+ *   Scratch: that of rawalign_dtw_batch plus 12 bytes per pair, per (device,
+ *   stream).  The reverse pass sweeps sum(e + 1) * n cells.
+ */
+int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, float *out_score, int32_t *out_end, int32_t *out_start, void *stream,
+                      const rawalign_opts *opts);
+
+/*
  * Global DTW between two anchors (Sec. 2.4.2, anchor-guided alignment): a
  * chain's anchors sit at the upper-left and lower-right corners of every gap
  * between them, and the signals they cover are not aligned again, so the

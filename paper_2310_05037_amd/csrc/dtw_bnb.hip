@@ -232,6 +232,9 @@ void k_bnb_run(BnbArgs b, float *edge_base) {
         pv.r = a.r + a.r_off[p];
         pv.m = a.r_len[p];
         pv.row = a.rows + a.row_off[p];
+        pv.corner = false;    // subsequence alignment, forward
+        pv.fixed_end = false;
+        pv.reverse = false;
         const int n = pv.n;   // >= 1, m >= 1 (others were settled before)
         int S, h;
         bnb_shape(pv.m, S, h);

@@ -108,10 +108,12 @@ RA_DEV __amdgpu_buffer_rsrc_t make_rsrc(const float *p, int n) {
 }
 
 // Element t (clamped to [0, nm1]) of a buffer, read at one uniform address by
-// every lane; only lane 0 keeps it after the DPP shift.
-RA_DEV float uload(__amdgpu_buffer_rsrc_t rs, int t, int nm1) {
+// every lane; only lane 0 keeps it after the DPP shift.  rev: element nm1 - t
+// instead (query read back to front).
+RA_DEV float uload(__amdgpu_buffer_rsrc_t rs, int t, int nm1, bool rev = false) {
     const int tt = t < nm1 ? t : nm1;
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, tt * 4, 0));
+    const int ix = rev ? nm1 - tt : tt;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, ix * 4, 0));
 }
 
 RA_DEV float bload(__amdgpu_buffer_rsrc_t rs, int idx) {
@@ -151,8 +153,10 @@ struct PairView {
     const float *r;
     int m;
     float *row;   // resident row (streaming) or null
-    bool fresh;   // row -1 is all zero (subsequence) or the global boundary
-    bool global;  // corner entry at (0, 0), exit at (n-1, m-1)
+    bool fresh;              // row -1 is the boundary (not a resident row)
+    bool corner = false;     // boundary: only the corner D(-1,-1) = 0, the rest of row -1 +inf
+    bool fixed_end = false;  // result: D(n-1, m-1) instead of the minimum of row n-1
+    bool reverse = false;    // query and region read back to front
 };
 
 template <bool EXT>
@@ -164,7 +168,9 @@ RA_DEV PairView pair_view(const PairArrays &a, int p) {
     pv.m = a.r_len[p];
     pv.row = EXT ? a.rows + a.row_off[p] : nullptr;
     pv.fresh = EXT ? a.first_chunk[p] != 0 : true;
-    pv.global = !EXT && a.global != 0;
+    pv.corner = !EXT && a.bound != kBoundSubseq;
+    pv.fixed_end = !EXT && a.bound == kBoundGlobal;
+    pv.reverse = !EXT && a.reverse != 0;
     return pv;
 }
 
@@ -188,14 +194,16 @@ RA_DEV bool slices_ok(const PairArrays &a, int64_t p, bool extend) {
 RA_DEV bool tiny_pair(const PairArrays &a, int64_t p) {
     const int n = a.q_len[p];
     const int m = a.r_len[p];
-    return a.global && n >= 1 && m >= 1 && m <= kTinyMaxCols && slices_ok(a, p, false);
+    return a.bound == kBoundGlobal && !a.reverse && n >= 1 && m >= 1 && m <= kTinyMaxCols &&
+           slices_ok(a, p, false);
 }
 
 // Registers of one lane: levels, the double-buffered DP row.  Columns are
 // tested against lim = m - col0 (one register) rather than by their index,
 // so no per-column index stays live through the sweep.  Row -1 is zero for
-// a fresh subsequence alignment, +inf for a global one (its corner
-// D(-1,-1) = 0 enters through lane 0's north-west value instead).
+// a fresh subsequence alignment, +inf for the corner boundary (its corner
+// D(-1,-1) = 0 enters through lane 0's north-west value instead).  Reversed
+// pairs read column j from r[m-1-j].
 template <int C, bool EXT>
 RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C], float (&B)[C]) {
     const int lim = pv.m - col0;
@@ -203,11 +211,11 @@ RA_DEV void load_lane(const PairView &pv, int col0, float (&rv)[C], float (&A)[C
     const __amdgpu_buffer_rsrc_t rrs = make_rsrc(pv.r, pv.m);
     __amdgpu_buffer_rsrc_t wrs = rrs;
     if (EXT) wrs = make_rsrc(pv.row, pv.m);
-    const float row0 = pv.global ? kInf : 0.0f;
+    const float row0 = pv.corner ? kInf : 0.0f;
 #pragma unroll
     for (int s = 0; s < C; ++s) {
         const int jc = col0 + (s < last ? s : last);   // clamped into the region
-        const float lv = bload(rrs, jc);
+        const float lv = bload(rrs, pv.reverse ? pv.m - 1 - jc : jc);
         rv[s] = s < lim ? lv : 0.0f;   // padding columns: finite, never reported
         float init = row0;
         if (EXT && !pv.fresh) {
@@ -227,7 +235,7 @@ RA_DEV void finish_lane(const PairView &pv, int col0, const float (&A)[C], float
     const int lim = pv.m - col0;
     best = kInf;
     bj = 0x7fffffff;
-    if (!EXT && pv.global) {
+    if (!EXT && pv.fixed_end) {
 #pragma unroll
         for (int s = 0; s < C; ++s)
             if (s == lim - 1) take_min(best, bj, A[s], col0 + s);
@@ -307,7 +315,7 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
         // 0 the corner D(-1,-1) of a subsequence alignment may be 0, but then
         // D(-1,0) = 0 as well, so +inf gives the same minimum; a global
         // alignment enters through that corner, which is 0.
-        float E0 = kInf, E1 = pv.global ? 0.0f : kInf, qv = 0.0f, qo = 0.0f;
+        float E0 = kInf, E1 = pv.corner ? 0.0f : kInf, qv = 0.0f, qo = 0.0f;
         if (EIN) E1 = corner;   // row 0's north-west neighbour left of this stripe
         const __amdgpu_buffer_rsrc_t qrs = make_rsrc(pv.q, n);
         const __amdgpu_buffer_rsrc_t ers = make_rsrc(edge, n);
@@ -318,7 +326,8 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
         const int ta = T < skew ? T : skew;     // end of the masked fill
         int tb = n & ~1;                        // end of the unmasked middle
         if (tb < ta) tb = ta;
-        float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
+        const bool qrev = pv.reverse;
+        float qa = uload(qrs, 0, nm1, qrev), qb = uload(qrs, 1, nm1, qrev);
         float ea = 0.0f, eb = 0.0f;
         if (EIN) {
             ea = uload(ers, 0, nm1);
@@ -328,8 +337,8 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
 #define RA_STEPS(MASKED)                                                                     \
     {                                                                                        \
         const float q0 = qa, q1 = qb, e0 = ea, e1 = eb;                                      \
-        qa = uload(qrs, t + 2, nm1);                                                         \
-        qb = uload(qrs, t + 3, nm1);                                                         \
+        qa = uload(qrs, t + 2, nm1, qrev);                                                   \
+        qb = uload(qrs, t + 3, nm1, qrev);                                                   \
         if (EIN) {                                                                           \
             ea = uload(ers, t + 2, nm1);                                                     \
             eb = uload(ers, t + 3, nm1);                                                     \

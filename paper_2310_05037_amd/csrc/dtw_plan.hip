@@ -27,7 +27,7 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
         end = -2;
         return -1;
     }
-    if (a.global) {
+    if (a.bound == kBoundGlobal) {
         // Anchors touching diagonally cost 0; a gap with events but no
         // levels (or levels but no events) has no path: +inf.
         if (n == 0 || m == 0) {
@@ -35,7 +35,7 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
             end = -1;
             return -1;
         }
-        if (m <= kTinyMaxCols) return -2;
+        if (m <= kTinyMaxCols && !a.reverse) return -2;
     }
     if (n == 0 && fresh) {
         score = 0.0f;
@@ -177,6 +177,37 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
     hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(kPlanBlock), 0, stream, pa);
     hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
     hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(kPlanBlock), 0, stream, pa);
+    return hipGetLastError();
+}
+
+// ---- alignment start -------------------------------------------------------------
+
+// The reverse pass aligns the reversed query against the reversed region
+// prefix r[0 .. end]: end + 1 levels (none for a pair without an end).
+__global__ void k_span_prep(const int32_t *__restrict__ end, int64_t n_pairs, int32_t *__restrict__ rev_len) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_pairs) rev_len[p] = end[p] >= 0 ? end[p] + 1 : 0;
+}
+
+// Its best end k (smallest on ties) is the forward column end - k: the
+// latest start among the optimal paths ending at end.  Pairs without an
+// end keep their sentinel (-1 degenerate, -2 invalid).
+__global__ void k_span_finish(const int32_t *__restrict__ end, const int32_t *__restrict__ rev_end, int64_t n_pairs,
+                              int32_t *__restrict__ out_start) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_pairs) out_start[p] = end[p] >= 0 ? end[p] - rev_end[p] : end[p];
+}
+
+hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_len, hipStream_t stream) {
+    const unsigned g = (unsigned)((n_pairs + 255) / 256);
+    hipLaunchKernelGGL(k_span_prep, dim3(g), dim3(256), 0, stream, end, n_pairs, rev_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_t n_pairs, int32_t *out_start,
+                              hipStream_t stream) {
+    const unsigned g = (unsigned)((n_pairs + 255) / 256);
+    hipLaunchKernelGGL(k_span_finish, dim3(g), dim3(256), 0, stream, end, rev_end, n_pairs, out_start);
     return hipGetLastError();
 }
 

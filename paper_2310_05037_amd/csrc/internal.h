@@ -82,11 +82,22 @@ struct PairArrays {
     int64_t rows_size;
     const int64_t *row_off;
     const uint8_t *first_chunk;
-    // 1: global alignment between two anchors (Sec. 2.4.2): the path enters
-    // at (0, 0) from the corner D(-1,-1) = 0 and leaves at (n-1, m-1); the
-    // rest of row -1 is +inf.  0: subsequence alignment.
-    int global = 0;
+    // Boundary and result (BoundMode): subsequence, global between anchors,
+    // or anchored start with a free end.
+    int bound = 0;
+    // 1: read query and region back to front: query element t is
+    // q[n-1-t], region column j is r[m-1-j].
+    int reverse = 0;
 };
+
+// Boundary and result of an alignment:
+//   kBoundSubseq:   row -1 zero (free start), C = min of the last row;
+//   kBoundGlobal:   global between two anchors (Sec. 2.4.2): the path enters
+//                   at (0, 0) from the corner D(-1,-1) = 0, the rest of row
+//                   -1 is +inf, and the result is D(n-1, m-1);
+//   kBoundAnchored: the corner boundary with the subsequence result: the
+//                   reverse pass that finds where an alignment starts.
+enum BoundMode : int { kBoundSubseq = 0, kBoundGlobal = 1, kBoundAnchored = 2 };
 
 // Global pairs of at most kTinyMaxCols levels are aligned one pair per lane
 // (dtw_global.hip); the planning of the striped kernels leaves them out.
@@ -159,6 +170,11 @@ hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *can
                          hipStream_t stream);
 hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, hipStream_t stream);
 hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *streams);
+// Alignment start: the reverse pass's region lengths (end + 1) and, after
+// it, start = end - (reverse pass end).
+hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_len, hipStream_t stream);
+hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_t n_pairs, int32_t *out_start,
+                              hipStream_t stream);
 hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
                             const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
                             hipStream_t stream);

@@ -71,6 +71,14 @@ struct BnbStore {
 };
 std::map<std::pair<int, hipStream_t>, BnbStore> g_bnb;
 
+// Alignment-start scratch, per (device, stream): the reverse pass's region
+// lengths, scores and ends (12 bytes per pair), grown on demand.
+struct SpanStore {
+    void *mem = nullptr;
+    int64_t pairs = 0;
+};
+std::map<std::pair<int, hipStream_t>, SpanStore> g_span;
+
 struct TimingRecord {
     hipEvent_t ev[8] = {};
     bool valid = false;
@@ -262,7 +270,8 @@ struct Call {
     const int64_t *row_off;
     const uint8_t *first_chunk;
     hipStream_t stream;
-    bool global = false;   // global alignment between anchors (Sec. 2.4.2)
+    int bound = ra::kBoundSubseq;   // ra::BoundMode
+    bool reverse = false;           // query and region read back to front
 };
 
 int check_call(const Call &c) {
@@ -272,7 +281,8 @@ int check_call(const Call &c) {
     if (c.q_size >= ((int64_t)1 << 40) || c.r_size >= ((int64_t)1 << 40))
         return fail(RAWALIGN_EINVAL, "q_size and r_size must be < 2^40");
     if (c.n_pairs == 0) return RAWALIGN_OK;
-    if (!c.q_off || !c.q_len || !c.r_off || !c.r_len || !c.out_score || (!c.out_end && !c.global))
+    if (!c.q_off || !c.q_len || !c.r_off || !c.r_len || !c.out_score ||
+        (!c.out_end && c.bound != ra::kBoundGlobal))
         return fail(RAWALIGN_EINVAL, "null pointer argument");
     if ((c.q_size > 0 && !c.q) || (c.r_size > 0 && !c.r)) return fail(RAWALIGN_EINVAL, "null data pointer");
     if (c.rows && (!c.row_off || !c.first_chunk || c.rows_size < 0))
@@ -289,8 +299,9 @@ int run(const Call &c, const rawalign_opts &o) {
     if (rc) return rc;
     if (c.rows && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
         return fail(RAWALIGN_EINVAL, "extend: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
-    if (c.global && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
-        return fail(RAWALIGN_EINVAL, "global alignment: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
+    if ((c.bound != ra::kBoundSubseq || c.reverse) && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
+        return fail(RAWALIGN_EINVAL, "global alignment and alignment starts: opts.long_kernel must be "
+                                     "RAWALIGN_LONG_STRIPED");
     if (c.n_pairs == 0) return RAWALIGN_OK;
     int dev = 0;
     DeviceInfo info;
@@ -331,9 +342,11 @@ int run(const Call &c, const rawalign_opts &o) {
     a.rows_size = c.rows_size;
     a.row_off = c.row_off;
     a.first_chunk = c.first_chunk;
-    a.global = c.global ? 1 : 0;
+    a.bound = c.bound;
+    a.reverse = c.reverse ? 1 : 0;
     const ra::PlanScratch ps = plan_view(*s);
-    if (c.global) {
+    const bool tiny = c.bound == ra::kBoundGlobal && !c.reverse;
+    if (tiny) {
         rc = get_tiny(*s, c.n_pairs);
         if (rc) return rc;
     }
@@ -342,7 +355,7 @@ int run(const Call &c, const rawalign_opts &o) {
     if (timing && (e = hipEventRecord(s->ev[0], c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "plan kernels");
-    if (c.global) {
+    if (tiny) {
         e = ra::launch_tiny_plan(a, c.n_pairs, tiny_view(*s), c.stream);
         if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane planning");
     }
@@ -355,7 +368,7 @@ int run(const Call &c, const rawalign_opts &o) {
             if ((e = hipStreamWaitEvent(st[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
     }
-    if (c.global) {
+    if (tiny) {
         e = ra::launch_tiny(a, tiny_view(*s), info.cus, st);
         if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
     }
@@ -629,8 +642,61 @@ int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_o
     o.long_waves_per_cu = 1;
     if (opts) o = *opts;
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
-           nullptr, 0, nullptr, nullptr, (hipStream_t)stream, true};
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream, ra::kBoundGlobal};
     return run(c, o);
+}
+
+int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, float *out_score, int32_t *out_end, int32_t *out_start, void *stream,
+                      const rawalign_opts *opts) {
+    const rawalign_opts o = effective_opts(opts);
+    if (o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
+        return fail(RAWALIGN_EINVAL, "alignment starts: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
+    if (n_pairs > 0 && !out_start) return fail(RAWALIGN_EINVAL, "null pointer argument: out_start");
+    const hipStream_t st = (hipStream_t)stream;
+    // Forward: cost and end column of every pair.
+    Call fwd{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+             nullptr, 0, nullptr, nullptr, st};
+    int rc = run(fwd, o);
+    if (rc || n_pairs == 0) return rc;
+    int dev = 0;
+    DeviceInfo info;
+    rc = device_info(dev, info);
+    if (rc) return rc;
+    int32_t *rev_len, *rev_end;
+    float *rev_score;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        SpanStore &sp = g_span[{dev, st}];
+        if (sp.pairs < n_pairs) {
+            int64_t cap = sp.pairs ? sp.pairs : 1024;
+            while (cap < n_pairs) cap *= 2;
+            if (sp.mem) (void)hipFree(sp.mem);
+            sp.mem = nullptr;
+            sp.pairs = 0;
+            hipError_t e = hipMalloc(&sp.mem, (size_t)cap * 12);
+            if (e != hipSuccess) {
+                sp.mem = nullptr;
+                return alloc_fail(e);
+            }
+            sp.pairs = cap;
+        }
+        rev_len = (int32_t *)sp.mem;
+        rev_end = rev_len + sp.pairs;
+        rev_score = (float *)(rev_end + sp.pairs);
+    }
+    hipError_t e = ra::launch_span_prep(out_end, n_pairs, rev_len, st);
+    if (e != hipSuccess) return hip_fail(e, "span kernels");
+    // Backward: the reversed query against the reversed prefix r[0 .. end],
+    // anchored at the end cell, free to finish anywhere.
+    Call bwd{q, q_size, q_off, q_len, r, r_size, r_off, rev_len, n_pairs, rev_score, rev_end,
+             nullptr, 0, nullptr, nullptr, st, ra::kBoundAnchored, true};
+    rc = run(bwd, o);
+    if (rc) return rc;
+    e = ra::launch_span_finish(out_end, rev_end, n_pairs, out_start, st);
+    if (e != hipSuccess) return hip_fail(e, "span kernels");
+    return RAWALIGN_OK;
 }
 
 int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,

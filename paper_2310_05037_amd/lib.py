@@ -32,7 +32,7 @@ FLAG_TIMING = 1
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
     "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
-    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_global_batch", "rawalign_chain_decide",
+    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_global_batch", "rawalign_chain_decide",
     "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing", "rawalign_last_error", "rawalign_version",
 )
 
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.rawalign_map_bnb.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp, i64, f64, f64, i32, i32,
                                    vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_dtw_global_batch.argtypes = pair_args + [ctypes.POINTER(Opts)]
+    L.rawalign_dtw_span.argtypes = pair_args[:11] + [vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_chain_decide.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts)]
@@ -212,6 +213,15 @@ def rawalign_decide(score, cand_off, cand_cnt, n_events, out_best, out_score, ou
                                   float(threshold), _dev(out_best, torch.int32, "out_best"),
                                   _dev(out_score, torch.float64, "out_score"),
                                   _dev(out_mapped, torch.uint8, "out_mapped"), _stream(stream)))
+
+
+def rawalign_dtw_span(q, q_off, q_len, r, r_off, r_len, out_score, out_end, out_start, opts=None, stream=None):
+    import torch
+    a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
+    if out_start.numel() != a[8]:
+        raise ValueError(f"out_start has {out_start.numel()} elements, expected {a[8]}")
+    _check(load().rawalign_dtw_span(*a, _dev(out_start, torch.int32, "out_start"), _stream(stream),
+                                    None if opts is None else ctypes.byref(opts)))
 
 
 def rawalign_dtw_global_batch(q, q_off, q_len, r, r_off, r_len, out_score, out_end=None, opts=None, stream=None):
