@@ -78,8 +78,18 @@ def cpu_baseline(b, seconds: float):
         done_pairs += len(idx)
         chunk = min(chunk * 2, 4096)
     dt = time.perf_counter() - t0
+    # the same recurrence on one core, over the next pairs of the same order, about 3 s
+    one_cells, one_pairs, t1 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t1 < min(3.0, seconds) and done_pairs + one_pairs < b.n_pairs:
+        sub = b.subset(order[done_pairs + one_pairs:done_pairs + one_pairs + 1])
+        oracle.dtw_batch_f64(sub.q, sub.q_off, sub.q_len, sub.r, sub.r_off, sub.r_len, 1)
+        one_cells += sub.cells
+        one_pairs += 1
+    dt1 = time.perf_counter() - t1
     return {"value": done_cells / dt / 1e9, "unit": "GCUPS", "cores": int(used), "kind": "oracle",
-            "sample": f"{done_pairs} random pairs ({done_cells:.3e} cells, {dt:.1f} s), float64 recurrence"}
+            "sample": f"{done_pairs} random pairs ({done_cells:.3e} cells, {dt:.1f} s), float64 recurrence",
+            "one_core": {"value": one_cells / dt1 / 1e9, "unit": "GCUPS", "cores": 1,
+                         "sample": f"{one_pairs} further pairs ({one_cells:.3e} cells, {dt1:.1f} s)"}}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_multi_uneven_batch_traffic.txt")
