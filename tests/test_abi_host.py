@@ -103,6 +103,18 @@ def test_argument_errors_without_device(L):
     rc = so.rawalign_dtw_global_batch(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, None, None,
                                       ctypes.byref(o))
     assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
+    # alignment start: out_start required, striped long kernel only, zero pairs is a no-op
+    rc = so.rawalign_dtw_span(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, None, None)
+    assert rc == L.RAWALIGN_EINVAL and b"out_start" in so.rawalign_last_error()
+    o = L.opts_default()
+    o.long_kernel = L.LONG_ANTIDIAG
+    rc = so.rawalign_dtw_span(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, fake, None,
+                              ctypes.byref(o))
+    assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_span(None, 0, None, None, None, 0, None, None, 0, None, None, None, None, None)
+    assert rc == L.RAWALIGN_OK
+    rc = so.rawalign_dtw_span(fake, 10, fake, fake, fake, 10, fake, fake, -3, fake, fake, fake, None, None)
+    assert rc == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
     # chain sums and decision
     def chains(n_gaps=4, n_chains=2, n_reads=1, gap_cost=fake, events=fake, threshold=20.0):
         return so.rawalign_chain_decide(gap_cost, n_gaps, fake, fake, events, n_chains, fake, fake, n_reads, 0.4,
