@@ -204,6 +204,64 @@ def bnb_leg(lib, b, opts, steps: int = 3, block_rows: int = 512):
             "entry_point": "rawalign_map_bnb"}
 
 
+def single_read_leg(lib, reps: int = 300):
+    """The single-read workload (one read of 1,566 events against 10 regions
+    of 895 levels): latency per read with the inputs on the device, and end
+    to end: the read's events and pair tables copied from pinned host memory,
+    DTW, decision, results copied back to pinned host memory.  The reference
+    levels stay resident, as a mapper's index would.  Ten pairs cannot fill
+    the GPU, so this is latency, not throughput."""
+    import torch
+    from paper_2310_05037_amd import workloads
+    b = workloads.single_read()
+    db = lib.DeviceBatch(b)
+    stream = torch.cuda.current_stream()
+    dev = db.q.device
+    cand_off = torch.zeros(1, dtype=torch.int64, device=dev)
+    cand_cnt = torch.full((1,), b.n_pairs, dtype=torch.int32, device=dev)
+    n_events = torch.full((1,), int(b.q_len[0]), dtype=torch.int32, device=dev)
+    outs = [torch.empty(1, dtype=t, device=dev) for t in (torch.int32, torch.float64, torch.uint8)]
+    opts = lib.make_opts()
+
+    def run_device():
+        db.run(opts=opts, stream=stream)
+        lib.rawalign_decide(db.score, cand_off, cand_cnt, n_events, *outs, stream=stream)
+    for _ in range(20):
+        run_device()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run_device()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    device_us = e0.elapsed_time(e1) / reps * 1e3
+    # end to end from pinned host buffers
+    h_q = torch.from_numpy(b.q).pin_memory()
+    h_tab = [torch.from_numpy(np.ascontiguousarray(x)).pin_memory() for x in (b.q_off, b.q_len, b.r_off, b.r_len)]
+    d_tab = [db.q_off, db.q_len, db.r_off, db.r_len]
+    h_out = [torch.empty(b.n_pairs, dtype=torch.float32).pin_memory(),
+             torch.empty(b.n_pairs, dtype=torch.int32).pin_memory()] + \
+            [torch.empty(1, dtype=t).pin_memory() for t in (torch.int32, torch.float64, torch.uint8)]
+    lat = []
+    for k in range(reps + 20):
+        t0 = time.perf_counter()
+        db.q.copy_(h_q, non_blocking=True)
+        for d, h in zip(d_tab, h_tab):
+            d.copy_(h, non_blocking=True)
+        run_device()
+        for h, d in zip(h_out, [db.score, db.end] + outs):
+            h.copy_(d, non_blocking=True)
+        stream.synchronize()
+        if k >= 20:
+            lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+    return {"device_us_per_read": device_us, "end_to_end_ms_p50": float(np.percentile(lat, 50)),
+            "end_to_end_ms_p99": float(np.percentile(lat, 99)), "pairs": b.n_pairs, "cells": b.cells,
+            "best_is_true_region": bool(int(h_out[2][0]) == int(b.true_pair[0])), "mapped": bool(int(h_out[4][0])),
+            "workload": "single_read_10_pairs", "reps": reps}
+
+
 def span_leg(lib, db, opts, steps: int = 3):
     """Scores, ends and starts of the same batch (rawalign_dtw_span: the
     forward pass, then the reversed query against each region prefix up to
@@ -365,6 +423,8 @@ def main():
         variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
     if not args.skip_anchored:
         variants["anchored"] = anchored_leg(lib, valu_peak)
+    if not args.skip_plain:
+        variants["single_read"] = single_read_leg(lib)
 
     # dominant kernel: the route with the largest average duration
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}

@@ -205,13 +205,17 @@ static int tiny_occupancy() {
 
 // Widest class first: its longest gaps are the longest serial chains.
 template <int C>
-static hipError_t launch_tiny_class(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
+static hipError_t launch_tiny_class(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus,
+                                    const hipStream_t *st) {
     if constexpr (C >= 0) {
-        const unsigned grid = (unsigned)(cus * tiny_occupancy<C>());
+        // no more waves than 64 pairs each could need
+        const int64_t need = (n_pairs + 63) / 64;
+        const int64_t full = (int64_t)cus * tiny_occupancy<C>();
+        const unsigned grid = (unsigned)(need < full ? need : full);
         hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[(kTinyClasses - 1 - C) % 3], a, t, C);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_tiny_class<C - 1>(a, t, cus, st);
+        return launch_tiny_class<C - 1>(a, n_pairs, t, cus, st);
     }
     return hipSuccess;
 }
@@ -229,8 +233,8 @@ hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScra
 // The width classes go round the three streams, widest first: each class is
 // about one round of waves, whose time its longest gaps set, so classes on
 // different streams overlap.
-hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *st) {
-    return launch_tiny_class<kTinyClasses - 1>(a, t, cus, st);
+hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus, const hipStream_t *st) {
+    return launch_tiny_class<kTinyClasses - 1>(a, n_pairs, t, cus, st);
 }
 
 // ---- chain sums ------------------------------------------------------------------

@@ -169,7 +169,8 @@ hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *can
                          int32_t *out_best, double *out_score, uint8_t *out_mapped, bool per_candidate,
                          hipStream_t stream);
 hipError_t launch_tiny_plan(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, hipStream_t stream);
-hipError_t launch_tiny(const PairArrays &a, const TinyScratch &t, int cus, const hipStream_t *streams);
+hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus,
+                       const hipStream_t *streams);
 // Alignment start: the reverse pass's region lengths (end + 1) and, after
 // it, start = end - (reverse pass end).
 hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_len, hipStream_t stream);

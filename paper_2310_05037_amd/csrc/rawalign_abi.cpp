@@ -318,6 +318,16 @@ int run(const Call &c, const rawalign_opts &o) {
     // CU; by default at most 4, since each holds a 256 KiB row buffer.
     const int ad_occ = ra::antidiag_blocks_per_cu();
     cfg.antidiag_grid = info.cus * std::min(o.long_waves_per_cu ? o.long_waves_per_cu : 4, ad_occ);
+    // A persistent grid never needs more workgroups than the batch has pairs
+    // (a small batch would otherwise launch thousands of waves that only
+    // start and exit).
+    {
+        const int cap = (int)std::min<int64_t>(c.n_pairs, 1 << 30);
+        cfg.lo_grid = std::min(cfg.lo_grid, cap);
+        cfg.hi_grid = std::min(cfg.hi_grid, cap);
+        cfg.multi_grid = std::min(cfg.multi_grid, cap);
+        cfg.antidiag_grid = std::min(cfg.antidiag_grid, cap);
+    }
     const bool antidiag = o.long_kernel == RAWALIGN_LONG_ANTIDIAG;
 
     const bool timing = (o.flags & RAWALIGN_FLAG_TIMING) != 0;
@@ -369,7 +379,7 @@ int run(const Call &c, const rawalign_opts &o) {
         }
     }
     if (tiny) {
-        e = ra::launch_tiny(a, tiny_view(*s), info.cus, st);
+        e = ra::launch_tiny(a, c.n_pairs, tiny_view(*s), info.cus, st);
         if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
     }
     // Longest regions first: they bound the makespan.
@@ -593,7 +603,8 @@ int rawalign_map_bnb(const float *q, int64_t q_size, const int64_t *q_off, const
     hipError_t e;
     if (n_pairs > 0) {
         // One persistent wave per resident slot, each with its own stripe edge slot.
-        const int grid = grid_of(info.cus, o.long_waves_per_cu, ra::bnb_blocks_per_cu());
+        const int grid = (int)std::min<int64_t>(grid_of(info.cus, o.long_waves_per_cu, ra::bnb_blocks_per_cu()),
+                                                n_pairs);
         StreamScratch *ss = nullptr;
         rc = get_scratch(dev, st, n_pairs, grid, 0, false, false, ss);
         if (rc) return rc;
