@@ -156,3 +156,57 @@ def test_anchored_chains_full_size(L):
     ab = W.anchored_chains()
     acc, mapped = _check_anchored(ab, _gpu_anchored(L, ab))
     print("anchored full: gaps", ab.n_gaps, "cells", ab.cells, "true chain wins", acc, "mapped", mapped)
+
+
+def test_chain_decide_edge_cases(L):
+    """Chains without gaps (cost 0), a gap range past the end (NaN), a read
+    without chains, tied scores (smallest chain index wins), an infinite gap
+    cost, another match bonus and threshold: chain costs bit for bit and
+    decisions equal to the oracle's."""
+    import torch
+    dev = "cuda"
+    gap = np.array([2.0 ** 24, 1.0, 1.0, 1.5, 2.25, np.inf, 0.5, 0.5], np.float32)
+    chain_off = np.array([0, 3, 5, 6, 6, 7, 7], np.int64)
+    chain_cnt = np.array([3, 2, 1, 0, 1, 1, 5], np.int32)     # the last range runs past the gaps
+    events = np.array([100, 50, 60, 40, 30, 30, 90], np.int32)
+    cand_off = np.array([0, 2, 3, 4, 7], np.int64)
+    cand_cnt = np.array([2, 1, 1, 3, 0], np.int32)          # read 4 has no chains
+    t = lambda x: torch.from_numpy(x).to(dev)
+    cc = torch.empty(len(chain_off), dtype=torch.float32, device=dev)
+    outs = [torch.empty(len(cand_off), dtype=d, device=dev) for d in (torch.int32, torch.float64, torch.uint8)]
+    for bm, th in ((0.4, 20.0), (0.3, 5.0)):
+        L.rawalign_chain_decide(t(gap), t(chain_off), t(chain_cnt), t(events), t(cand_off), t(cand_cnt), cc, *outs,
+                                b_match=bm, threshold=th)
+        torch.cuda.synchronize()
+        exp = oracle.chain_costs(gap, chain_off, chain_cnt)
+        got = cc.cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), exp.view(np.uint32))
+        assert np.isnan(got[6]) and got[3] == 0.0 and got[2] == np.inf
+        rb, rs, rm = oracle.decide_chains(exp, events, cand_off, cand_cnt, bm, th)
+        ob, os_, om = (o.cpu().numpy() for o in outs)
+        assert np.array_equal(ob, rb) and np.array_equal(om, rm)
+        assert np.array_equal(os_[:4].view(np.uint64), rs[:4].view(np.uint64))
+        assert ob[4] == -1 and os_[4] == -np.inf and om[4] == 0
+        # read 3: chains 4 (30*b - 0.5) and 5 (30*b - 0.5) tie; chain 6 is NaN
+        assert ob[3] == 4
+
+
+def test_span_three_streams_equals_one(L):
+    """The start pass on three internal streams gives the same bits as on
+    one."""
+    import torch
+    rng = np.random.default_rng(12)
+    b = W.random_pairs(rng, 500, (1, 300), (1, 5000))
+    res = []
+    for streams in (1, 3):
+        db = L.DeviceBatch(b)
+        st = torch.empty(b.n_pairs, dtype=torch.int32, device="cuda")
+        L.rawalign_dtw_span(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, db.score, db.end, st,
+                            opts=L.make_opts(streams=streams))
+        torch.cuda.synchronize()
+        res.append((db.score.cpu().numpy(), db.end.cpu().numpy(), st.cpu().numpy()))
+    (s1, e1, t1), (s3, e3, t3) = res
+    assert np.array_equal(s1.view(np.uint32), s3.view(np.uint32)) and np.array_equal(e1, e3)
+    assert np.array_equal(t1, t3)
+    s32, e32, st32 = oracle.dtw_span_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
+    assert np.array_equal(s1.view(np.uint32), s32.view(np.uint32)) and np.array_equal(t1, st32)
