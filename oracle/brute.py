@@ -128,3 +128,33 @@ def brute_span(q, r):
     cost = min(c for c, _ in best.values())
     end = min(j for j, (c, _) in best.items() if c == cost)
     return cost, end, best[end][1]
+
+
+def brute_band(q, r, w):
+    """(cost, end) of banded subsequence DTW by enumeration: every
+    subsequence path (as brute_dtw) whose cells all satisfy
+    |j - floor(i*m/n)| <= w; the cheapest cost, the smallest final column.
+    No path: (+inf, -1)."""
+    q = [float(x) for x in q]
+    r = [float(x) for x in r]
+    n, m = len(q), len(r)
+    if n == 0:
+        return 0.0, -1
+    if m == 0:
+        return math.inf, -1
+
+    def ok(i, j):
+        return abs(j - (i * m) // n) <= w
+
+    best, best_end = math.inf, -1
+    stack = [(0, j0, abs(q[0] - r[j0])) for j0 in range(m) if ok(0, j0)]
+    while stack:
+        i, j, acc = stack.pop()
+        if i == n - 1:
+            if acc < best or (acc == best and j < best_end):
+                best, best_end = acc, j
+        for di, dj in ((1, 0), (0, 1), (1, 1)):
+            i2, j2 = i + di, j + dj
+            if i2 < n and j2 < m and ok(i2, j2):
+                stack.append((i2, j2, acc + abs(q[i2] - r[j2])))
+    return best, best_end

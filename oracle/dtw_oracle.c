@@ -400,6 +400,111 @@ float oracle_dtw_span_f32(const float *q, int64_t n, const float *r, int64_t m, 
     return c;
 }
 
+/*
+ * Banded subsequence DTW (Sec. 2.4.3): only cells near the diagonal of slope
+ * n/m are computed, the band following that diagonal rather than the slope 1
+ * one.  Reading: the diagonal column of row i is c(i) = floor(i*m/n); a
+ * cell (i,j) is in the band iff |j - c(i)| <= w (half-width w >= 0, in
+ * levels; a band w = 0.2*m wide on each side is 0.2*n rows from the
+ * diagonal, the paper's 20% of the fragment).  Cells outside the band are
+ * +inf; row -1 stays the free start (all zero) and column -1 +inf; the
+ * result is the minimum over row n-1 (band cells only), smallest j; +inf and
+ * end -1 when no cell of row n-1 is reachable.  n == 0: (0, -1); m == 0:
+ * (+inf, -1).  w >= m-1 puts every cell in the band: plain subsequence DTW.
+ */
+double oracle_dtw_band_f64(const float *q, int64_t n, const float *r, int64_t m, int64_t w, int32_t *end)
+{
+    if (n == 0 || m == 0) {
+        *end = -1;
+        return n == 0 ? 0.0 : INFINITY;
+    }
+    double *prev = malloc((size_t)(m + 1) * sizeof(double));
+    double *cur = malloc((size_t)(m + 1) * sizeof(double));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        *end = -2;
+        return NAN;
+    }
+    for (int64_t j = 0; j <= m; ++j)
+        prev[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = i * m / n;
+        cur[0] = INFINITY;
+        double qi = (double)q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            if (j < c - w || j > c + w) {
+                cur[j + 1] = INFINITY;
+                continue;
+            }
+            double d = fabs(qi - (double)r[j]);
+            cur[j + 1] = d + min3_d(prev[j], prev[j + 1], cur[j]);
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    double best = INFINITY;
+    int32_t arg = -1;
+    for (int64_t j = 0; j < m; ++j) {
+        if (prev[j + 1] < best) {
+            best = prev[j + 1];
+            arg = (int32_t)j;
+        }
+    }
+    free(prev);
+    free(cur);
+    *end = arg;
+    return best;
+}
+
+float oracle_dtw_band_f32(const float *q, int64_t n, const float *r, int64_t m, int64_t w, int32_t *end)
+{
+    if (n == 0 || m == 0) {
+        *end = -1;
+        return n == 0 ? 0.0f : INFINITY;
+    }
+    float *prev = malloc((size_t)(m + 1) * sizeof(float));
+    float *cur = malloc((size_t)(m + 1) * sizeof(float));
+    if (!prev || !cur) {
+        free(prev);
+        free(cur);
+        *end = -2;
+        return NAN;
+    }
+    for (int64_t j = 0; j <= m; ++j)
+        prev[j] = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = i * m / n;
+        cur[0] = INFINITY;
+        float qi = q[i];
+        for (int64_t j = 0; j < m; ++j) {
+            if (j < c - w || j > c + w) {
+                cur[j + 1] = INFINITY;
+                continue;
+            }
+            float d = qi - r[j];
+            float a = fabsf(d);
+            cur[j + 1] = a + min3_f(prev[j], prev[j + 1], cur[j]);
+        }
+        float *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    float best = INFINITY;
+    int32_t arg = -1;
+    for (int64_t j = 0; j < m; ++j) {
+        if (prev[j + 1] < best) {
+            best = prev[j + 1];
+            arg = (int32_t)j;
+        }
+    }
+    free(prev);
+    free(cur);
+    *end = arg;
+    return best;
+}
+
 /* ---- batches: pairs are independent, threads take pairs from a counter ---- */
 
 struct batch_job {
@@ -415,6 +520,7 @@ struct batch_job {
     int32_t *out_end;   /* NULL for global alignment (no end column) */
     int global;
     int32_t *out_start; /* span: start column per pair */
+    const int32_t *band; /* banded: half-width per pair */
     int64_t next;
 };
 
@@ -427,7 +533,14 @@ static void *batch_worker(void *arg)
             break;
         const float *qp = job->q + job->q_off[p];
         const float *rp = job->r + job->r_off[p];
-        if (job->out_start) {
+        if (job->band) {
+            if (job->out64)
+                job->out64[p] = oracle_dtw_band_f64(qp, job->q_len[p], rp, job->r_len[p], job->band[p],
+                                                    &job->out_end[p]);
+            else
+                job->out32[p] = oracle_dtw_band_f32(qp, job->q_len[p], rp, job->r_len[p], job->band[p],
+                                                    &job->out_end[p]);
+        } else if (job->out_start) {
             if (job->out64)
                 job->out64[p] = oracle_dtw_span_f64(qp, job->q_len[p], rp, job->r_len[p], &job->out_end[p],
                                                     &job->out_start[p]);
@@ -478,7 +591,7 @@ int oracle_dtw_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, out_end, 0, NULL, 0};
+                            out_score, NULL, out_end, 0, NULL, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -488,7 +601,7 @@ int oracle_dtw_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_
                          int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, out_end, 0, NULL, 0};
+                            NULL, out_score, out_end, 0, NULL, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -498,7 +611,7 @@ int oracle_dtw_global_batch_f64(const float *q, const int64_t *q_off, const int3
                                 int64_t n_pairs, double *out_score, int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, NULL, 1, NULL, 0};
+                            out_score, NULL, NULL, 1, NULL, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -507,7 +620,7 @@ int oracle_dtw_global_batch_f32(const float *q, const int64_t *q_off, const int3
                                 int64_t n_pairs, float *out_score, int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, NULL, 1, NULL, 0};
+                            NULL, out_score, NULL, 1, NULL, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -518,7 +631,7 @@ int oracle_dtw_span_batch_f64(const float *q, const int64_t *q_off, const int32_
                               int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            out_score, NULL, out_end, 0, out_start, 0};
+                            out_score, NULL, out_end, 0, out_start, NULL, 0};
     return run_batch(&job, n_threads);
 }
 
@@ -528,6 +641,25 @@ int oracle_dtw_span_batch_f32(const float *q, const int64_t *q_off, const int32_
                               int n_threads)
 {
     struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
-                            NULL, out_score, out_end, 0, out_start, 0};
+                            NULL, out_score, out_end, 0, out_start, NULL, 0};
+    return run_batch(&job, n_threads);
+}
+
+/* Banded subsequence DTW of every pair (band: half-width per pair). */
+int oracle_dtw_band_batch_f64(const float *q, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, const int64_t *r_off, const int32_t *r_len, const int32_t *band,
+                              int64_t n_pairs, double *out_score, int32_t *out_end, int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            out_score, NULL, out_end, 0, NULL, band, 0};
+    return run_batch(&job, n_threads);
+}
+
+int oracle_dtw_band_batch_f32(const float *q, const int64_t *q_off, const int32_t *q_len,
+                              const float *r, const int64_t *r_off, const int32_t *r_len, const int32_t *band,
+                              int64_t n_pairs, float *out_score, int32_t *out_end, int n_threads)
+{
+    struct batch_job job = {q, q_off, q_len, r, r_off, r_len, n_pairs,
+                            NULL, out_score, out_end, 0, NULL, band, 0};
     return run_batch(&job, n_threads);
 }

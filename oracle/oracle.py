@@ -16,6 +16,8 @@ with the HIP library.
   output): the read aligned backwards against the region prefix ending at
   the end column, anchored there, free to finish anywhere; ties give the
   largest start (the shortest optimal alignment).
+* ``dtw_band_*``: banded subsequence DTW of Sec. 2.4.3: cells farther than
+  w levels from the diagonal column floor(i*m/n) are +inf.
 * ``dtw_global_*`` / ``chain_costs`` / ``decide_chains``: anchor-guided
   alignment of Sec. 2.4.2: every gap between two consecutive anchors of a
   chain is aligned by global DTW entered and left through the anchor corners;
@@ -72,6 +74,14 @@ def lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, i32p, ctypes.c_int]
+        L.oracle_dtw_band_f64.restype = ctypes.c_double
+        L.oracle_dtw_band_f64.argtypes = [f32p, i64, f32p, i64, i64, i32p]
+        L.oracle_dtw_band_f32.restype = ctypes.c_float
+        L.oracle_dtw_band_f32.argtypes = [f32p, i64, f32p, i64, i64, i32p]
+        for name, outp in (("oracle_dtw_band_batch_f64", f64p), ("oracle_dtw_band_batch_f32", f32p)):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i32p, i64, outp, i32p, ctypes.c_int]
         L.oracle_dtw_span_f64.restype = ctypes.c_double
         L.oracle_dtw_span_f64.argtypes = [f32p, i64, f32p, i64, i32p, i32p]
         L.oracle_dtw_span_f32.restype = ctypes.c_float
@@ -353,3 +363,55 @@ def dtw_span_batch_f64(q, q_off, q_len, r, r_off, r_len, threads=None):
 def dtw_span_batch_f32(q, q_off, q_len, r, r_off, r_len, threads=None):
     """(scores f32, ends, starts) of every pair with float arithmetic."""
     return _span_batch(lib().oracle_dtw_span_batch_f32, np.float32, q, q_off, q_len, r, r_off, r_len, threads)
+
+
+# ---- banded alignment (Sec. 2.4.3) -------------------------------------------------
+
+def dtw_band_f64(q, r, w):
+    """(C_DTW, end) of banded subsequence DTW with half-width w, double."""
+    q = _f32(q)
+    r = _f32(r)
+    e = ctypes.c_int32(0)
+    c = lib().oracle_dtw_band_f64(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r), int(w),
+                                  ctypes.byref(e))
+    return c, e.value
+
+
+def dtw_band_f32(q, r, w):
+    """The same with every value in float."""
+    q = _f32(q)
+    r = _f32(r)
+    e = ctypes.c_int32(0)
+    c = lib().oracle_dtw_band_f32(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r), int(w),
+                                  ctypes.byref(e))
+    return np.float32(c), e.value
+
+
+def _band_batch(fn, dtype, q, q_off, q_len, r, r_off, r_len, band, threads):
+    q = _f32(q)
+    r = _f32(r)
+    q_off = np.ascontiguousarray(q_off, dtype=np.int64)
+    r_off = np.ascontiguousarray(r_off, dtype=np.int64)
+    q_len = np.ascontiguousarray(q_len, dtype=np.int32)
+    r_len = np.ascontiguousarray(r_len, dtype=np.int32)
+    band = np.ascontiguousarray(band, dtype=np.int32)
+    n = len(q_off)
+    assert len(q_len) == n and len(r_off) == n and len(r_len) == n and len(band) == n
+    score = np.empty(n, dtype=dtype)
+    end = np.empty(n, dtype=np.int32)
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    if n:
+        ct = ctypes.c_double if dtype == np.float64 else ctypes.c_float
+        fn(_ptr(q, ctypes.c_float), _ptr(q_off, ctypes.c_int64), _ptr(q_len, ctypes.c_int32),
+           _ptr(r, ctypes.c_float), _ptr(r_off, ctypes.c_int64), _ptr(r_len, ctypes.c_int32),
+           _ptr(band, ctypes.c_int32), n, _ptr(score, ct), _ptr(end, ctypes.c_int32), int(threads))
+    return score, end
+
+
+def dtw_band_batch_f64(q, q_off, q_len, r, r_off, r_len, band, threads=None):
+    return _band_batch(lib().oracle_dtw_band_batch_f64, np.float64, q, q_off, q_len, r, r_off, r_len, band, threads)
+
+
+def dtw_band_batch_f32(q, q_off, q_len, r, r_off, r_len, band, threads=None):
+    return _band_batch(lib().oracle_dtw_band_batch_f32, np.float32, q, q_off, q_len, r, r_off, r_len, band, threads)
