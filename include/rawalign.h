@@ -244,6 +244,26 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
                       const rawalign_opts *opts);
 
 /*
+ * Banded subsequence DTW (Sec. 2.4.3): only the cells near the diagonal of
+ * slope n/m are computed.  Row i's diagonal column is c(i) = floor(i*m/n);
+ * cell (i, j) is in the band iff |j - c(i)| <= band[p] (half-width in
+ * levels; 20% of the fragment, the paper's default, is about 0.2*m); other
+ * cells are +inf.  Row -1 is the free start, and the result is the minimum
+ * over the band cells of row n-1 (smallest j), +inf with end -1 when none is
+ * reachable.  band[p] >= m-1 gives plain subsequence DTW.
+ *   Arguments as in rawalign_dtw_batch, plus band (device, int32 per pair).
+ *   One wave per pair in a band-relative frame (frame positions follow the
+ *   diagonal), pairs in arrival order from a persistent queue.
+ *   Supported shapes: m <= n (at least as many events as levels, as in a
+ *   chained segment: about 3.3 events per level) and 2*min(band, m-1)+1 <=
+ *   2048; other pairs get the sentinel NaN, end -4.  A negative band or an
+ *   invalid slice gives NaN, -2; n == 0 gives (0, -1), m == 0 (+inf, -1).
+ */
+int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      const int32_t *band, int64_t n_pairs, float *out_score, int32_t *out_end, void *stream);
+
+/*
  * Global DTW between two anchors (Sec. 2.4.2, anchor-guided alignment): a
  * chain's anchors sit at the upper-left and lower-right corners of every gap
  * between them, and the signals they cover are not aligned again, so the

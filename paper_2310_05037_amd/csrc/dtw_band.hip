@@ -1,0 +1,291 @@
+// dtw_band.hip -- banded subsequence DTW (RawAlign, arXiv 2310.05037, Sec.
+// 2.4.3): only cells within w levels of the diagonal column c(i) =
+// floor(i*m/n) of row i are computed; the others are +inf.  Row -1 is the
+// free start (zero), column -1 +inf, and the result is the minimum over the
+// band cells of row n-1 (smallest column).
+//
+// Band-relative lane-striped layout, one wave64 per pair:
+//   * the frame of row i is the 64*C columns starting at f(i) = c(i) - w;
+//     lane k owns frame positions [kC, kC+C), so the W = 2w+1 band columns
+//     sit in positions [0, W) of every row;
+//   * the sweep is skewed as in the full-table kernels (lane k computes row
+//     t - k at step t); query events and the west neighbour move one lane
+//     down per step with DPP wave_shr:1;
+//   * chained segments have at least as many events as levels, so the frame
+//     moves right by s = c(i) - c(i-1) in {0, 1} per row.  When it moves, a
+//     lane's levels and previous-row values shift down by one position; the
+//     value entering its last position comes from lane k+1 (its first
+//     position, computed earlier in the same step: the lanes run in lockstep)
+//     through DPP wave_shl:1, and lane 63's new level from a uniform load
+//     issued two steps ahead;
+//   * frame positions at or past W are outside the band.  The only one a band
+//     cell reads is position W of the previous row (north of position W-1
+//     when the frame moves), so that cell is forced to +inf every row.
+// Per cell: the two shift selects, v_sub_f32, v_min3_f32 and v_add_f32.
+#include "dtw_device.h"
+
+namespace ra {
+
+constexpr int kDppWaveShl1 = 0x130;   // DPP control: whole-wave shift left by one lane
+
+// Lanes 0..62 receive `src` from lane+1; lane 63 keeps `old_v`.
+RA_DEV float dpp_shl1(float old_v, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old_v),
+                                                                 __builtin_bit_cast(int, src),
+                                                                 kDppWaveShl1, 0xF, 0xF, false));
+}
+
+RA_DEV int dpp_shr1_i(int old_v, int src) {
+    return __builtin_amdgcn_update_dpp(old_v, src, kDppWaveShr1, 0xF, 0xF, false);
+}
+
+// Band state of one pair that every lane shares.
+struct BandView {
+    const float *q;
+    const float *r;
+    int n, m, w, W;
+};
+
+// Uniform row counter: c = floor(row*m/n) with rem = row*m mod n, advanced
+// one row at a time (m <= n: at most one carry per row).
+struct RowCounter {
+    int c, rem;
+};
+
+RA_DEV int advance(RowCounter &rc, int m, int n) {
+    rc.rem += m;
+    const int carry = rc.rem >= n ? 1 : 0;
+    rc.rem -= carry ? n : 0;
+    rc.c += carry;
+    return carry;
+}
+
+// Level at column j of the region, +inf outside [0, m) (uniform address).
+RA_DEV float level_or_inf(__amdgpu_buffer_rsrc_t rs, int j, int m) {
+    const int jc = j < 0 ? 0 : (j >= m ? m - 1 : j);
+    const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, jc * 4, 0));
+    return (j < 0 || j >= m) ? kInf : v;
+}
+
+// Forces the previous-row value at frame position W (lane kk, register vk)
+// to +inf; vk is uniform, so the switch is a scalar branch.
+template <int C>
+RA_DEV void kill_slot(float (&An)[C], int vk, bool mine) {
+    switch (vk) {
+#define RA_KILL(V)                                    \
+    case V:                                           \
+        if constexpr (V < C) An[V] = mine ? kInf : An[V]; \
+        break;
+        RA_KILL(1) RA_KILL(2) RA_KILL(3) RA_KILL(4) RA_KILL(5) RA_KILL(6) RA_KILL(7) RA_KILL(8)
+        RA_KILL(9) RA_KILL(10) RA_KILL(11) RA_KILL(12) RA_KILL(13) RA_KILL(14) RA_KILL(15) RA_KILL(16)
+        RA_KILL(17) RA_KILL(18) RA_KILL(19) RA_KILL(20) RA_KILL(21) RA_KILL(22) RA_KILL(23) RA_KILL(24)
+        RA_KILL(25) RA_KILL(26) RA_KILL(27) RA_KILL(28) RA_KILL(29) RA_KILL(30) RA_KILL(31)
+#undef RA_KILL
+        default:
+            break;
+    }
+}
+
+// One step: row i of this lane (frame shift sh) from Ao to An.
+//   qv: the row's event; el: west value of position 0 (row i); ed: the west
+//   value of the previous step (row i-1, frame i-1); r63: lane 63's new
+//   level when its frame moves; kill_x: this lane must treat its incoming
+//   north value as +inf (position W is lane k+1's first position).
+template <int C, bool MASKED>
+RA_DEV void band_step(bool valid, bool sh, float qv, float el, float ed, float r63, bool kill_x, int kill_v,
+                      bool kill_mine, float (&rv)[C], const float (&Ao)[C], float (&An)[C]) {
+    // levels of this row's frame
+    const float r0 = sh ? rv[1] : rv[0];
+    const float xr = dpp_shl1(r63, r0);
+#pragma unroll
+    for (int v = 0; v < C - 1; ++v) rv[v] = sh ? rv[v + 1] : rv[v];
+    rv[C - 1] = sh ? xr : rv[C - 1];
+    // previous row in this row's frame: U(v) = Ao(v + sh); U(-1) from the west
+    const float ud = sh ? Ao[0] : ed;
+    float up = sh ? Ao[1] : Ao[0];
+    float prev = fabsf(qv - rv[0]) + fminf(fminf(ud, up), el);
+    float xd = dpp_shl1(kInf, prev);
+    xd = kill_x ? kInf : xd;
+    An[0] = (MASKED && !valid) ? Ao[0] : prev;
+#pragma unroll
+    for (int v = 1; v < C; ++v) {
+        const float un = v < C - 1 ? (sh ? Ao[v + 1] : Ao[v]) : (sh ? xd : Ao[C - 1]);
+        prev = fabsf(qv - rv[v]) + fminf(fminf(up, un), prev);
+        up = un;
+        An[v] = (MASKED && !valid) ? Ao[v] : prev;
+    }
+    kill_slot<C>(An, kill_v, kill_mine);
+}
+
+template <int C>
+RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
+    const int lane = opaque_lane();
+    const int n = bv.n, m = bv.m, w = bv.w, W = bv.W;
+    const __amdgpu_buffer_rsrc_t rrs = make_rsrc(bv.r, m);
+    const __amdgpu_buffer_rsrc_t qrs = make_rsrc(bv.q, n);
+    // Row -1 (all zero: free start) in row 0's frame f(0) = -w.
+    float rv[C], A[C], B[C];
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        const int j = lane * C + v - w;
+        const int jc = j < 0 ? 0 : (j >= m ? m - 1 : j);
+        const float lv = bload(rrs, jc);
+        rv[v] = (j < 0 || j >= m) ? kInf : lv;
+        A[v] = 0.0f;
+        B[v] = 0.0f;
+    }
+    // Position W: static kill of the incoming value when it is a lane's
+    // first position, else a register of lane W / C.
+    const int F = 64 * C;
+    const bool has_kill = W < F;
+    const int kk = W / C, kv = W % C;
+    const bool kill_x = has_kill && kv == 0 && lane == kk - 1;
+    const int kill_v = has_kill && kv != 0 ? kv : 0;   // 0: no register kill
+    const bool kill_mine = lane == kk;
+    // Uniform counters: lane 0's row t (shift injected at step t) and lane
+    // 63's row t - 63 + 2 (its new level, loaded two steps ahead).
+    RowCounter c0{0, 0}, c63{0, 0};
+    int row63 = -61;   // row of c63
+    const int nm1 = n - 1;
+    // el: west value of position 0 from the previous step.  Its initial 0 is
+    // row -1 (free start): lane 0's north-west value at row 0; later lane 0
+    // injects +inf (west of the band).
+    float qv = 0.0f, el = 0.0f;
+    int sv = 0;
+    float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
+    float ra = kInf, rb = kInf;   // lane 63's new levels for steps t, t+1
+    int sa = 0, sb = 0;           // shifts injected at steps t, t+1 (rows t, t+1)
+    // rows 0 and 1: s_0 = 0 (row -1 is in row 0's frame), s_1 = c(1) - c(0)
+    sb = n > 1 ? advance(c0, m, n) : 0;
+    const int T = (n + 65) & ~1;
+    const int ta = T < 64 ? T : 64;
+    int tb = n & ~1;
+    if (tb < ta) tb = ta;
+    int t = 0;
+    auto next_r63 = [&](void) -> float {
+        // advance lane 63's look-ahead row; its frame top is f(row) + F - 1
+        float v = kInf;
+        if (row63 >= 1 && row63 < n) {
+            advance(c63, m, n);
+            v = level_or_inf(rrs, c63.c - w + F - 1, m);
+        }
+        ++row63;
+        return v;
+    };
+#define RA_BAND_STEPS(MASKED)                                                                  \
+    {                                                                                         \
+        const float q0 = qa, q1 = qb, r0v = ra, r1v = rb;                                     \
+        const int s0 = sa, s1 = sb;                                                           \
+        qa = uload(qrs, t + 2, nm1);                                                          \
+        qb = uload(qrs, t + 3, nm1);                                                          \
+        sa = (t + 2 < n) ? advance(c0, m, n) : 0;                                             \
+        sb = (t + 3 < n) ? advance(c0, m, n) : 0;                                             \
+        ra = next_r63();                                                                      \
+        rb = next_r63();                                                                      \
+        {                                                                                     \
+            qv = dpp_shr1(q0, qv);                                                            \
+            sv = dpp_shr1_i(s0, sv);                                                          \
+            const float eprev = el;                                                           \
+            el = dpp_shr1(kInf, A[C - 1]);                                                    \
+            const bool valid = (unsigned)(t - lane) < (unsigned)n;                            \
+            band_step<C, MASKED>(valid, valid && sv != 0, qv, el, eprev, r0v, kill_x, kill_v, \
+                                 kill_mine, rv, A, B);                                        \
+        }                                                                                     \
+        {                                                                                     \
+            qv = dpp_shr1(q1, qv);                                                            \
+            sv = dpp_shr1_i(s1, sv);                                                          \
+            const float eprev = el;                                                           \
+            el = dpp_shr1(kInf, B[C - 1]);                                                    \
+            const bool valid = (unsigned)(t + 1 - lane) < (unsigned)n;                        \
+            band_step<C, MASKED>(valid, valid && sv != 0, qv, el, eprev, r1v, kill_x, kill_v, \
+                                 kill_mine, rv, B, A);                                        \
+        }                                                                                     \
+    }
+    for (; t < ta; t += 2) RA_BAND_STEPS(true)
+    for (; t < tb; t += 2) RA_BAND_STEPS(false)
+    for (; t < T; t += 2) RA_BAND_STEPS(true)
+#undef RA_BAND_STEPS
+    // Row n-1 in its frame f(n-1) = c(n-1) - w.
+    const int f_end = (int)((int64_t)(n - 1) * m / n) - w;
+    best = kInf;
+    bj = 0x7fffffff;
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        const int u = lane * C + v;
+        const int j = f_end + u;
+        if (u < W && j >= 0 && j < m) take_min(best, bj, A[v], j);
+    }
+    wave_min(best, bj);
+    if (!(best < kInf)) bj = -1;
+}
+
+template <int H>
+RA_DEV void band_dispatch(int h, const BandView &bv, float &best, int &bj) {
+    if constexpr (H <= 16) {
+        if (h == H)
+            band_pair<2 * H>(bv, best, bj);
+        else
+            band_dispatch<H + 1>(h, bv, best, bj);
+    }
+}
+
+constexpr int kBandMaxFrame = 64 * 32;   // band columns one wave takes (C <= 32)
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_band(PairArrays a, const int32_t *__restrict__ band, int64_t n_pairs, int32_t *queue) {
+    int it = 0;
+    if (__lane_id() == 0) it = atomicAdd(queue, 1);
+    int64_t p = __builtin_amdgcn_readfirstlane(it);
+    while (p < n_pairs) {
+        const int n = a.q_len[p];
+        const int m = a.r_len[p];
+        const int wraw = band[p];
+        float best = __builtin_nanf("");
+        int bj = -2;
+        if (!slices_ok(a, p, false) || wraw < 0) {
+            // invalid slice or band: NaN, -2
+        } else if (n == 0) {
+            best = 0.0f;
+            bj = -1;
+        } else if (m == 0) {
+            best = kInf;
+            bj = -1;
+        } else {
+            // w >= m-1 admits every column of every row: same band
+            const int w = wraw < m - 1 ? wraw : m - 1;
+            const int W = 2 * w + 1;
+            if (m > n || W > kBandMaxFrame) {
+                bj = -4;   // shape the banded kernel does not take: NaN, -4
+            } else {
+                BandView bv{a.q + a.q_off[p], a.r + a.r_off[p], n, m, w, W};
+                const int h = (W + 127) / 128;   // C = 2h columns per lane, 64 C >= W
+                band_dispatch<1>(h, bv, best, bj);
+            }
+        }
+        if (__lane_id() == 0) {
+            a.out_score[p] = best;
+            a.out_end[p] = bj;
+        }
+        if (__lane_id() == 0) it = atomicAdd(queue, 1);
+        p = __builtin_amdgcn_readfirstlane(it);
+    }
+}
+
+__global__ void k_band_zero(int32_t *queue) {
+    if (threadIdx.x == 0) *queue = 0;
+}
+
+hipError_t launch_band(const PairArrays &a, const int32_t *band, int64_t n_pairs, int grid, int32_t *queue,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL(k_band_zero, dim3(1), dim3(64), 0, stream, queue);
+    hipLaunchKernelGGL(k_band, dim3((unsigned)grid), dim3(64), 0, stream, a, band, n_pairs, queue);
+    return hipGetLastError();
+}
+
+int band_blocks_per_cu() {
+    int nb = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_band, 64, 0);
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace ra

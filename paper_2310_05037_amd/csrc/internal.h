@@ -176,6 +176,11 @@ hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &
 hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_len, hipStream_t stream);
 hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_t n_pairs, int32_t *out_start,
                               hipStream_t stream);
+// Banded subsequence DTW: one wave per pair, pairs taken from `queue`
+// (zeroed by the launch) in arrival order.
+hipError_t launch_band(const PairArrays &a, const int32_t *band, int64_t n_pairs, int grid, int32_t *queue,
+                       hipStream_t stream);
+int band_blocks_per_cu();
 hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
                             const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
                             hipStream_t stream);

@@ -710,6 +710,43 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
     return RAWALIGN_OK;
 }
 
+int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      const int32_t *band, int64_t n_pairs, float *out_score, int32_t *out_end, void *stream) {
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
+    int rc = check_call(c);
+    if (rc) return rc;
+    if (n_pairs == 0) return RAWALIGN_OK;
+    if (!band) return fail(RAWALIGN_EINVAL, "null pointer argument: band");
+    int dev = 0;
+    DeviceInfo info;
+    rc = device_info(dev, info);
+    if (rc) return rc;
+    StreamScratch *s = nullptr;
+    rc = get_scratch(dev, c.stream, 0, 0, 0, false, false, s);
+    if (rc) return rc;
+    ra::PairArrays a;
+    a.q = q;
+    a.q_size = q_size;
+    a.q_off = q_off;
+    a.q_len = q_len;
+    a.r = r;
+    a.r_size = r_size;
+    a.r_off = r_off;
+    a.r_len = r_len;
+    a.out_score = out_score;
+    a.out_end = out_end;
+    a.rows = nullptr;
+    a.rows_size = 0;
+    a.row_off = nullptr;
+    a.first_chunk = nullptr;
+    const int grid = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(), n_pairs);
+    hipError_t e = ra::launch_band(a, band, n_pairs, grid, plan_view(*s).queue, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "banded kernel");
+    return RAWALIGN_OK;
+}
+
 int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
                           const int32_t *chain_gap_cnt, const int32_t *chain_events, int64_t n_chains,
                           const int64_t *cand_off, const int32_t *cand_cnt, int64_t n_reads, double b_match,

@@ -32,7 +32,8 @@ FLAG_TIMING = 1
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
     "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
-    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_global_batch", "rawalign_chain_decide",
+    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_band", "rawalign_dtw_global_batch",
+    "rawalign_chain_decide",
     "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing", "rawalign_last_error", "rawalign_version",
 )
 
@@ -86,6 +87,7 @@ def load(path: str = LIB_PATH):
                                    vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_dtw_global_batch.argtypes = pair_args + [ctypes.POINTER(Opts)]
     L.rawalign_dtw_span.argtypes = pair_args[:11] + [vp, vp, ctypes.POINTER(Opts)]
+    L.rawalign_dtw_band.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.rawalign_chain_decide.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
     L.rawalign_load_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(Opts)]
@@ -222,6 +224,14 @@ def rawalign_dtw_span(q, q_off, q_len, r, r_off, r_len, out_score, out_end, out_
         raise ValueError(f"out_start has {out_start.numel()} elements, expected {a[8]}")
     _check(load().rawalign_dtw_span(*a, _dev(out_start, torch.int32, "out_start"), _stream(stream),
                                     None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_dtw_band(q, q_off, q_len, r, r_off, r_len, band, out_score, out_end, stream=None):
+    import torch
+    a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
+    if band.numel() != a[8]:
+        raise ValueError(f"band has {band.numel()} elements, expected {a[8]}")
+    _check(load().rawalign_dtw_band(*a[:8], _dev(band, torch.int32, "band"), a[8], a[9], a[10], _stream(stream)))
 
 
 def rawalign_dtw_global_batch(q, q_off, q_len, r, r_off, r_len, out_score, out_end=None, opts=None, stream=None):

@@ -369,6 +369,8 @@ class AnchoredBatch:
     chain_gap_cnt: np.ndarray  # int32 per chain
     chain_events: np.ndarray   # int32 per chain
     chain_levels: np.ndarray   # int32 per chain: reference levels its anchors span
+    chain_q_off: np.ndarray    # int64 per chain: first event of its first anchor (index into q)
+    chain_r_off: np.ndarray    # int64 per chain: first level of its first anchor (index into r)
     cand_off: np.ndarray       # int64 per read
     cand_cnt: np.ndarray       # int32 per read
     true_chain: np.ndarray     # int64 per read
@@ -409,9 +411,9 @@ def _chain_gaps(anchors, ev_at, lv_at):
     but no levels (or levels but no events) has no path between the anchor
     corners; such a gap is merged with the following anchor and gap.
     Returns (list of (q offset, q length, r offset, r length), first event,
-    end event, levels spanned)."""
+    end event, levels spanned, first level)."""
     if not anchors:
-        return [], 0, 0, 0
+        return [], 0, 0, 0, 0
     kept = [anchors[0]]
     for a in anchors[1:]:
         prev_end = kept[-1][1]
@@ -425,7 +427,7 @@ def _chain_gaps(anchors, ev_at, lv_at):
         e0, e1 = ev_at(kept[t][1]), ev_at(kept[t + 1][0])
         l0, l1 = lv_at(kept[t][1]), lv_at(kept[t + 1][0])
         gaps.append((e0, e1 - e0, l0, l1 - l0))
-    return gaps, ev_at(kept[0][0]), ev_at(kept[-1][1]), lv_at(kept[-1][1]) - lv_at(kept[0][0])
+    return gaps, ev_at(kept[0][0]), ev_at(kept[-1][1]), lv_at(kept[-1][1]) - lv_at(kept[0][0]), lv_at(kept[0][0])
 
 
 def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_index: int = 5) -> AnchoredBatch:
@@ -449,7 +451,7 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
     reads = []
     read_base = []
     g_q_off, g_q_len, g_r_off, g_r_len = [], [], [], []
-    c_gap_off, c_gap_cnt, c_events, c_levels = [], [], [], []
+    c_gap_off, c_gap_cnt, c_events, c_levels, c_qoff, c_roff = [], [], [], [], [], []
     cand_cnt, true_chain = [], []
     q_pos = 0
     n_done = 0
@@ -465,8 +467,8 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
         for c in range(k):
             if c == 0:
                 anchors = _anchor_walk(rng, used)
-                gaps, e_first, e_end, levels = _chain_gaps(anchors, lambda u: int(ev_start[u]),
-                                                           lambda u: start + u)
+                gaps, e_first, e_end, levels, l_first = _chain_gaps(anchors, lambda u: int(ev_start[u]),
+                                                                    lambda u: start + u)
             else:
                 span = max(1, int(len(ev) * rng.uniform(0.2, 1.0)))
                 e0 = int(rng.integers(0, len(ev) - span + 1))
@@ -477,11 +479,14 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
                 d_start = np.concatenate([[0], np.cumsum(dwell)]).astype(np.int64)
                 d_start = np.minimum(d_start, span)
                 anchors = _anchor_walk(rng, kmers)
-                gaps, e_first, e_end, levels = _chain_gaps(anchors, lambda u: e0 + int(d_start[u]), lambda u: l0 + u)
+                gaps, e_first, e_end, levels, l_first = _chain_gaps(anchors, lambda u: e0 + int(d_start[u]),
+                                                                    lambda u: l0 + u)
             c_gap_off.append(len(g_q_off))
             c_gap_cnt.append(len(gaps))
             c_events.append(e_end - e_first)
             c_levels.append(levels)
+            c_qoff.append(q_pos + e_first)
+            c_roff.append(l_first)
             for (eo, el, lo, ll) in gaps:
                 g_q_off.append(q_pos + eo)
                 g_q_len.append(el)
@@ -497,7 +502,26 @@ def anchored_chains(n_chains: int = 100_000, ref_bases: int = 50_000_000, seed_i
                          np.array(g_q_off, dtype=np.int64), np.array(g_q_len, dtype=np.int32),
                          np.array(g_r_off, dtype=np.int64), np.array(g_r_len, dtype=np.int32),
                          np.array(c_gap_off, dtype=np.int64), np.array(c_gap_cnt, dtype=np.int32),
-                         np.array(c_events, dtype=np.int32), np.array(c_levels, dtype=np.int32), cand_off, cand_cnt,
+                         np.array(c_events, dtype=np.int32), np.array(c_levels, dtype=np.int32),
+                         np.array(c_qoff, dtype=np.int64), np.array(c_roff, dtype=np.int64), cand_off, cand_cnt,
                          np.array(true_chain, dtype=np.int64),
                          {"seed_index": seed_index, "reference_bases": ref_bases,
                           "anchor_kmers": list(ANCHOR_KMERS), "gap_mean_kmers": GAP_MEAN_KMERS})
+
+
+BAND_FRACTION = 0.2   # Sec. 3.3: a band 20% of the fragment from the diagonal
+
+
+def chained_segments(ab: AnchoredBatch, band_fraction: float = BAND_FRACTION):
+    """Every chain of an anchored workload as one (segment, region) pair: the
+    read events from the chain's first anchor to its last against the
+    reference levels they span (what banded alignment of a whole chain
+    takes, Sec. 2.4.3), with half-width ceil(band_fraction * levels).
+    Returns (Batch, band int32 per pair)."""
+    k = ab.n_chains
+    b = Batch("chained_segments", ab.q, ab.r, ab.chain_q_off.copy(), ab.chain_events.copy(), ab.chain_r_off.copy(),
+              ab.chain_levels.copy(), ab.cand_off.copy(), ab.cand_cnt.copy(), ab.chain_events.copy(),
+              ab.true_chain.copy(), dict(ab.meta, band_fraction=band_fraction))
+    band = np.ceil(band_fraction * ab.chain_levels.astype(np.float64)).astype(np.int32)
+    assert len(band) == k
+    return b, band

@@ -1,0 +1,136 @@
+"""GPU parity of banded subsequence DTW (rawalign_dtw_band, Sec. 2.4.3)
+through the C ABI: scores and ends bit for bit against the float oracle over
+band widths from 0 to the whole table (every columns-per-lane class),
+exact against the double oracle on dyadic inputs, the unsupported shapes'
+sentinel, and the chained segments of the anchored workload."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2310_05037_amd import workloads as W
+
+from . import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2310_05037_amd import lib
+    assert torch.cuda.is_available()
+    lib.load()
+    return lib
+
+
+def _gpu_band(L, b, band):
+    import torch
+    print(f"  gpu: band {b.name} pairs={b.n_pairs} max_n={int(b.q_len.max()) if b.n_pairs else 0} "
+          f"max_m={int(b.r_len.max()) if b.n_pairs else 0} max_w={int(band.max()) if b.n_pairs else 0}", flush=True)
+    db = L.DeviceBatch(b)
+    L.rawalign_dtw_band(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len,
+                        torch.from_numpy(np.ascontiguousarray(band, dtype=np.int32)).cuda(), db.score, db.end)
+    torch.cuda.synchronize()
+    return db.score.cpu().numpy(), db.end.cpu().numpy()
+
+
+def _check(b, band, s, e, pairs=None):
+    sub = b if pairs is None else b.subset(pairs)
+    bd = band if pairs is None else band[pairs]
+    s32, e32 = oracle.dtw_band_batch_f32(sub.q, sub.q_off, sub.q_len, sub.r, sub.r_off, sub.r_len, bd,
+                                         parity.threads())
+    if pairs is not None:
+        s, e = s[pairs], e[pairs]
+    bad = np.flatnonzero((s.view(np.uint32) != s32.view(np.uint32)) | (e != e32))
+    assert len(bad) == 0, [(int(p), int(sub.q_len[p]), int(sub.r_len[p]), int(bd[p]), float(s[p]), float(s32[p]),
+                            int(e[p]), int(e32[p])) for p in bad[:8]]
+
+
+def _pairs(rng, ns, ms, name):
+    reads = [rng.standard_normal(int(n)).astype(np.float32) for n in ns]
+    r = rng.standard_normal(int(sum(ms)) + 3).astype(np.float32)
+    pairs, off = [], 0
+    for k, m in enumerate(ms):
+        pairs.append((k, off, int(m), False))
+        off += int(m)
+    return W._pack(name, reads, pairs, r, {})
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_band_widths_and_lane_classes(L, seed):
+    """Half-widths from 0 to past the table, frames from 128 to 2048 band
+    columns (every columns-per-lane class), slopes from 1 to 6 events per
+    level, short queries around the 64-lane skew."""
+    rng = np.random.default_rng(500 + seed)
+    ms, ns, ws = [], [], []
+    for w in [0, 1, 2, 5, 31, 63, 64, 65, 100, 191, 255, 300, 511, 700, 1000, 1023]:
+        m = int(rng.integers(max(2, w // 2), 1100))
+        n = int(m * rng.uniform(1.0, 6.0)) + int(rng.integers(0, 3))
+        ms.append(m), ns.append(n), ws.append(w)
+    for n, m in [(1, 1), (2, 1), (5, 5), (63, 40), (64, 64), (65, 30), (130, 129), (1000, 1000)]:
+        for w in (0, 3, m - 1, m + 5):
+            ms.append(m), ns.append(n), ws.append(max(w, 0))
+    b = _pairs(rng, ns, ms, f"band_widths_{seed}")
+    band = np.array(ws, np.int32)
+    s, e = _gpu_band(L, b, band)
+    _check(b, band, s, e)
+
+
+def test_band_full_width_equals_plain(L):
+    """band >= m-1 admits every cell: the banded kernel's results are the
+    plain batch's bit for bit."""
+    rng = np.random.default_rng(9)
+    b = W.random_pairs(rng, 300, (1, 400), (1, 400))
+    keep = np.flatnonzero(b.r_len <= b.q_len)
+    b = b.subset(keep)
+    band = (b.r_len + rng.integers(-1, 4, size=b.n_pairs)).astype(np.int32)
+    band = np.maximum(band, b.r_len - 1).astype(np.int32)
+    s, e = _gpu_band(L, b, band)
+    db = L.DeviceBatch(b)
+    db.run()
+    ps, pe = db.results()
+    assert np.array_equal(s.view(np.uint32), ps.view(np.uint32)) and np.array_equal(e, pe)
+
+
+def test_band_exact_on_dyadic_inputs(L):
+    rng = np.random.default_rng(10)
+    b = W.random_pairs(rng, 200, (50, 600), (1, 300), value_fn=lambda g, k: W.dyadic_values(g, k, -2.0, 2.0, 0.5))
+    keep = np.flatnonzero(b.r_len <= b.q_len)
+    b = b.subset(keep)
+    band = rng.integers(0, 200, size=b.n_pairs).astype(np.int32)
+    s, e = _gpu_band(L, b, band)
+    s64, e64 = oracle.dtw_band_batch_f64(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, band, parity.threads())
+    fin = np.isfinite(s64)
+    assert np.array_equal(s[fin].astype(np.float64), s64[fin]) and np.array_equal(e, e64)
+    assert np.isinf(s[~fin]).all()
+
+
+def test_band_sentinels(L):
+    """m > n and frames wider than 2048 columns: NaN, -4; a negative band
+    or an invalid slice: NaN, -2; empty query (0, -1); empty region
+    (+inf, -1)."""
+    rng = np.random.default_rng(11)
+    ns = [50, 3000, 20, 0, 10, 40, 40]
+    ms = [80, 2500, 10, 5, 0, 30, 30]
+    b = _pairs(rng, ns, ms, "band_sentinels")
+    band = np.array([5, 1100, -1, 3, 3, 4, 4], np.int32)
+    q_off = b.q_off.copy()
+    q_off[6] = len(b.q)           # slice past the end of q
+    b = W.Batch(b.name, b.q, b.r, q_off, b.q_len, b.r_off, b.r_len, b.cand_off, b.cand_cnt, b.n_events,
+                b.true_pair, b.meta)
+    s, e = _gpu_band(L, b, band)
+    assert math.isnan(s[0]) and e[0] == -4 and math.isnan(s[1]) and e[1] == -4
+    assert math.isnan(s[2]) and e[2] == -2 and math.isnan(s[6]) and e[6] == -2
+    assert s[3] == 0.0 and e[3] == -1 and s[4] == np.inf and e[4] == -1
+    _check(b, band, s, e, np.array([5]))
+
+
+def test_band_chained_segments(L):
+    """Whole chains of the anchored workload (about 3.3 events per level,
+    20% band): every pair bit for bit."""
+    ab = W.anchored_chains(6000, ref_bases=5_000_000)
+    b, band = W.chained_segments(ab)
+    s, e = _gpu_band(L, b, band)
+    _check(b, band, s, e)
