@@ -289,6 +289,61 @@ def span_leg(lib, db, opts, steps: int = 3):
             "mean_span_levels": float(np.mean(end - st + 1)), "entry_point": "rawalign_dtw_span"}
 
 
+def banded_leg(lib, valu_peak: float, opts=None, steps: int = 5, warmup: int = 1):
+    """Banded DTW (Sec. 2.4.3) of whole chains: the 100,000 chained segments
+    of the anchored workload (read events from the first anchor to the last
+    against the levels they span, about 3.3 events per level) with a band
+    20% of the segment on each side of the diagonal; the same pairs through
+    the full-table path beside it."""
+    import torch
+    from paper_2310_05037_amd import workloads
+    ab = workloads.anchored_chains()
+    b, band = workloads.chained_segments(ab)
+    db = lib.DeviceBatch(b)
+    dband = torch.from_numpy(band).to(db.q.device)
+    stream = torch.cuda.current_stream()
+
+    def run_band():
+        lib.rawalign_dtw_band(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, dband, db.score, db.end,
+                              stream=stream)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+    band_ms = timed(run_band)
+    end = db.end.cpu().numpy()
+    full_ms = timed(lambda: db.run(opts=opts, stream=stream))
+    n = b.q_len.astype(np.int64)
+    m = b.r_len.astype(np.int64)
+    w = np.minimum(band.astype(np.int64), m - 1)
+    # band cells: per row i, the columns of [c(i) - w, c(i) + w] inside [0, m),
+    # c(i) = floor(i m / n); counted over chunks of pairs to bound host memory
+    band_cells = 0
+    for lo in range(0, b.n_pairs, 10000):
+        nn, mm, ww = n[lo:lo + 10000], m[lo:lo + 10000], w[lo:lo + 10000]
+        rows = np.repeat(np.arange(len(nn)), nn)
+        i = np.arange(int(nn.sum())) - np.repeat(np.cumsum(nn) - nn, nn)
+        c = i * mm[rows] // nn[rows]
+        band_cells += int((np.minimum(c + ww[rows], mm[rows] - 1) - np.maximum(c - ww[rows], 0) + 1).sum())
+    frame_cells = int(np.dot(n, 128 * ((2 * w + 1 + 127) // 128)))
+    ops = VALU_OPS_PER_CELL * band_cells / (band_ms / 1e3)
+    return {"ms_per_batch": band_ms, "full_table_ms": full_ms, "pairs": b.n_pairs, "band_cells": band_cells,
+            "full_table_cells": b.cells, "frame_cells": frame_cells,
+            "band_gcups": band_cells / (band_ms / 1e3) / 1e9, "full_table_gcups": b.cells / (full_ms / 1e3) / 1e9,
+            "speedup_over_full_table": full_ms / band_ms, "unsupported_pairs": int((end == -4).sum()),
+            "roofline": {"bound": "alu", "achieved": ops / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
+                         "frac": ops / valu_peak, "over": "band cells at 3 VALU each"},
+            "entry_point": "rawalign_dtw_band", "workload": "chained_segments_100000"}
+
+
 def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
     """Anchor-guided alignment (Sec. 2.4.2) of 100,000 candidate chains of
     reads shaped like the uneven batch: global DTW of every gap between
@@ -336,6 +391,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="time only the tuned path (for profiling runs)")
     ap.add_argument("--skip-anchored", action="store_true", help="leave out the anchor-guided alignment leg")
+    ap.add_argument("--only-banded", action="store_true",
+                    help="run only the banded-DTW leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-anchored", action="store_true",
                     help="run only the anchor-guided alignment leg and print its JSON (for profiling runs)")
     ap.add_argument("--opts", type=str, default="", help="JSON dict of rawalign_opts fields for the tuned path")
@@ -366,6 +423,9 @@ def main():
     valu_peak = cus * LANES_PER_CU * CLOCK_HZ
     if args.only_anchored:
         print(json.dumps({"anchored": anchored_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
+    if args.only_banded:
+        print(json.dumps({"banded": banded_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
         return
 
     b = workloads.uneven_batch()
@@ -425,6 +485,8 @@ def main():
         variants["anchored"] = anchored_leg(lib, valu_peak)
     if not args.skip_plain:
         variants["single_read"] = single_read_leg(lib)
+    if not args.skip_anchored:
+        variants["banded"] = banded_leg(lib, valu_peak, lib.make_opts(**extra))
 
     # dominant kernel: the route with the largest average duration
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}

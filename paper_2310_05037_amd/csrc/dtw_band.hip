@@ -68,22 +68,19 @@ RA_DEV float level_or_inf(__amdgpu_buffer_rsrc_t rs, int j, int m) {
 }
 
 // Forces the previous-row value at frame position W (lane kk, register vk)
-// to +inf; vk is uniform, so the switch is a scalar branch.
+// to +inf.  vk is uniform: the register is picked by an indexed move on a
+// vector value (a switch over vk gets merged into one indexed store, which
+// sends the arrays to scratch memory).
 template <int C>
 RA_DEV void kill_slot(float (&An)[C], int vk, bool mine) {
-    switch (vk) {
-#define RA_KILL(V)                                    \
-    case V:                                           \
-        if constexpr (V < C) An[V] = mine ? kInf : An[V]; \
-        break;
-        RA_KILL(1) RA_KILL(2) RA_KILL(3) RA_KILL(4) RA_KILL(5) RA_KILL(6) RA_KILL(7) RA_KILL(8)
-        RA_KILL(9) RA_KILL(10) RA_KILL(11) RA_KILL(12) RA_KILL(13) RA_KILL(14) RA_KILL(15) RA_KILL(16)
-        RA_KILL(17) RA_KILL(18) RA_KILL(19) RA_KILL(20) RA_KILL(21) RA_KILL(22) RA_KILL(23) RA_KILL(24)
-        RA_KILL(25) RA_KILL(26) RA_KILL(27) RA_KILL(28) RA_KILL(29) RA_KILL(30) RA_KILL(31)
-#undef RA_KILL
-        default:
-            break;
-    }
+    typedef float vec_t __attribute__((ext_vector_type(C)));
+    vec_t x;
+#pragma unroll
+    for (int v = 0; v < C; ++v) x[v] = An[v];
+    const float cur = x[vk];
+    x[vk] = mine ? kInf : cur;
+#pragma unroll
+    for (int v = 0; v < C; ++v) An[v] = x[v];
 }
 
 // One step: row i of this lane (frame shift sh) from Ao to An.
