@@ -60,11 +60,12 @@ RA_DEV int advance(RowCounter &rc, int m, int n) {
     return carry;
 }
 
-// Level at column j of the region, +inf outside [0, m) (uniform address).
-RA_DEV float level_or_inf(__amdgpu_buffer_rsrc_t rs, int j, int m) {
-    const int jc = j < 0 ? 0 : (j >= m ? m - 1 : j);
-    const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, jc * 4, 0));
-    return (j < 0 || j >= m) ? kInf : v;
+// Level at column j >= 0 of the region, read at one uniform address (clamped
+// to the last level).  Past the region's end the caller uses +inf instead, at
+// the point where it consumes the value, so the load is not waited for here.
+RA_DEV float level_raw(__amdgpu_buffer_rsrc_t rs, int j, int m) {
+    const int jc = j < m ? j : m - 1;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, 0, jc * 4, 0));
 }
 
 // Forces the previous-row value at frame position W (lane kk, register vk)
@@ -151,6 +152,7 @@ RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
     int sv = 0;
     float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
     float ra = kInf, rb = kInf;   // lane 63's new levels for steps t, t+1
+    bool ra_in = false, rb_in = false;   // ... inside the region (else +inf)
     int sa = 0, sb = 0;           // shifts injected at steps t, t+1 (rows t, t+1)
     // rows 0 and 1: s_0 = 0 (row -1 is in row 0's frame), s_1 = c(1) - c(0)
     sb = n > 1 ? advance(c0, m, n) : 0;
@@ -159,26 +161,27 @@ RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
     int tb = n & ~1;
     if (tb < ta) tb = ta;
     int t = 0;
-    auto next_r63 = [&](void) -> float {
-        // advance lane 63's look-ahead row; its frame top is f(row) + F - 1
-        float v = kInf;
-        if (row63 >= 1 && row63 < n) {
-            advance(c63, m, n);
-            v = level_or_inf(rrs, c63.c - w + F - 1, m);
-        }
+    // Lane 63's look-ahead row and the level entering its frame top f(row) +
+    // F - 1 >= w >= 0 when that row's frame moves.  Rows before 1 never move
+    // and rows from n on are not computed, so their levels go unused.
+    auto next_r63 = [&](bool &in) -> float {
+        if (row63 >= 1) advance(c63, m, n);
         ++row63;
-        return v;
+        const int j = __builtin_amdgcn_readfirstlane(c63.c - w + F - 1);
+        in = j < m;
+        return level_raw(rrs, j, m);
     };
 #define RA_BAND_STEPS(MASKED)                                                                  \
     {                                                                                         \
-        const float q0 = qa, q1 = qb, r0v = ra, r1v = rb;                                     \
+        const float q0 = qa, q1 = qb;                                                         \
+        const float r0v = ra_in ? ra : kInf, r1v = rb_in ? rb : kInf;                         \
         const int s0 = sa, s1 = sb;                                                           \
         qa = uload(qrs, t + 2, nm1);                                                          \
         qb = uload(qrs, t + 3, nm1);                                                          \
         sa = (t + 2 < n) ? advance(c0, m, n) : 0;                                             \
         sb = (t + 3 < n) ? advance(c0, m, n) : 0;                                             \
-        ra = next_r63();                                                                      \
-        rb = next_r63();                                                                      \
+        ra = next_r63(ra_in);                                                                 \
+        rb = next_r63(rb_in);                                                                 \
         {                                                                                     \
             qv = dpp_shr1(q0, qv);                                                            \
             sv = dpp_shr1_i(s0, sv);                                                          \

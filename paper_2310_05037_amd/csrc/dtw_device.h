@@ -103,8 +103,18 @@ RA_DEV void row_step2(bool v1, bool v2, const float (&rv)[C], float q1, float q2
     }
 }
 
+// Buffer resource over n floats at p.  Every caller passes one pair's (or one
+// stripe's) pointer, the same in every lane of the wave; reading it from the
+// first lane tells the compiler so, which keeps the resource in scalar
+// registers.  Otherwise each buffer load in a sweep is wrapped in a loop
+// over the distinct resources of the active lanes.
 RA_DEV __amdgpu_buffer_rsrc_t make_rsrc(const float *p, int n) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, n * 4, kRsrcWord3);
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    const int bytes = __builtin_amdgcn_readfirstlane(n * 4);
+    float *base = reinterpret_cast<float *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, kRsrcWord3);
 }
 
 // Element t (clamped to [0, nm1]) of a buffer, read at one uniform address by
