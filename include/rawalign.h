@@ -253,7 +253,11 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
  * reachable.  band[p] >= m-1 gives plain subsequence DTW.
  *   Arguments as in rawalign_dtw_batch, plus band (device, int32 per pair).
  *   One wave per pair in a band-relative frame (frame positions follow the
- *   diagonal), pairs in arrival order from a persistent queue.
+ *   diagonal).  The pairs are planned on the device into two classes by
+ *   frame width (up to 512 columns, and wider), each taken longest first
+ *   from a persistent queue; the two class kernels run concurrently on
+ *   internal streams joined back to `stream`.  Scratch: that of
+ *   rawalign_dtw_batch, per (device, stream).
  *   Supported shapes: m <= n (at least as many events as levels, as in a
  *   chained segment: about 3.3 events per level) and 2*min(band, m-1)+1 <=
  *   2048; other pairs get the sentinel NaN, end -4.  A negative band or an

@@ -219,73 +219,75 @@ RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
     if (!(best < kInf)) bj = -1;
 }
 
-template <int H>
+// C = 2H columns per lane for H in [H, HMAX].
+template <int H, int HMAX>
 RA_DEV void band_dispatch(int h, const BandView &bv, float &best, int &bj) {
-    if constexpr (H <= 16) {
+    if constexpr (H <= HMAX) {
         if (h == H)
             band_pair<2 * H>(bv, best, bj);
         else
-            band_dispatch<H + 1>(h, bv, best, bj);
+            band_dispatch<H + 1, HMAX>(h, bv, best, bj);
     }
 }
 
-constexpr int kBandMaxFrame = 64 * 32;   // band columns one wave takes (C <= 32)
-
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_band(PairArrays a, const int32_t *__restrict__ band, int64_t n_pairs, int32_t *queue) {
+// Frames of 128(HLO-1)+1 .. 128 HHI columns.  Every listed pair is valid
+// and takes a frame in this range (the planner wrote the others' results).
+template <int HLO, int HHI, int WAVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES, WAVES)))
+void k_band(PairArrays a, const int32_t *__restrict__ band, const int32_t *__restrict__ list,
+            const int32_t *__restrict__ count, int32_t *queue) {
+    const int n_items = *count;
     int it = 0;
     if (__lane_id() == 0) it = atomicAdd(queue, 1);
-    int64_t p = __builtin_amdgcn_readfirstlane(it);
-    while (p < n_pairs) {
+    int item = __builtin_amdgcn_readfirstlane(it);
+    while (item < n_items) {
+        const int p = list[item];
         const int n = a.q_len[p];
         const int m = a.r_len[p];
         const int wraw = band[p];
+        // w >= m-1 admits every column of every row: same band
+        const int w = wraw < m - 1 ? wraw : m - 1;
+        const int W = 2 * w + 1;
+        const BandView bv{a.q + a.q_off[p], a.r + a.r_off[p], n, m, w, W};
+        const int h = (W + 127) / 128;   // C = 2h columns per lane, 64 C >= W
         float best = __builtin_nanf("");
         int bj = -2;
-        if (!slices_ok(a, p, false) || wraw < 0) {
-            // invalid slice or band: NaN, -2
-        } else if (n == 0) {
-            best = 0.0f;
-            bj = -1;
-        } else if (m == 0) {
-            best = kInf;
-            bj = -1;
-        } else {
-            // w >= m-1 admits every column of every row: same band
-            const int w = wraw < m - 1 ? wraw : m - 1;
-            const int W = 2 * w + 1;
-            if (m > n || W > kBandMaxFrame) {
-                bj = -4;   // shape the banded kernel does not take: NaN, -4
-            } else {
-                BandView bv{a.q + a.q_off[p], a.r + a.r_off[p], n, m, w, W};
-                const int h = (W + 127) / 128;   // C = 2h columns per lane, 64 C >= W
-                band_dispatch<1>(h, bv, best, bj);
-            }
-        }
+        band_dispatch<HLO, HHI>(h, bv, best, bj);
         if (__lane_id() == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;
         }
         if (__lane_id() == 0) it = atomicAdd(queue, 1);
-        p = __builtin_amdgcn_readfirstlane(it);
+        item = __builtin_amdgcn_readfirstlane(it);
     }
 }
 
-__global__ void k_band_zero(int32_t *queue) {
-    if (threadIdx.x == 0) *queue = 0;
-}
+// Class 0 (C <= 8) fits 64 VGPRs: eight waves per SIMD; class 1 four.
+#define RA_BAND_LO k_band<1, kBandLoMaxH, 8>
+#define RA_BAND_HI k_band<kBandLoMaxH + 1, kBandMaxFrame / 128, 4>
 
-hipError_t launch_band(const PairArrays &a, const int32_t *band, int64_t n_pairs, int grid, int32_t *queue,
+hipError_t launch_band(int cls, const PairArrays &a, const int32_t *band, int grid, const PlanScratch &s,
                        hipStream_t stream) {
-    hipLaunchKernelGGL(k_band_zero, dim3(1), dim3(64), 0, stream, queue);
-    hipLaunchKernelGGL(k_band, dim3((unsigned)grid), dim3(64), 0, stream, a, band, n_pairs, queue);
+    const int32_t *list = s.list + cls * s.capacity;
+    const int32_t *count = s.counts + cls;
+    int32_t *queue = s.queue + cls;
+    if (cls == 0)
+        hipLaunchKernelGGL(RA_BAND_LO, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
+    else
+        hipLaunchKernelGGL(RA_BAND_HI, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
     return hipGetLastError();
 }
 
-int band_blocks_per_cu() {
+int band_blocks_per_cu(int cls) {
     int nb = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_band, 64, 0);
+    if (cls == 0)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_LO, 64, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_HI, 64, 0);
     return nb > 0 ? nb : 1;
 }
+
+#undef RA_BAND_LO
+#undef RA_BAND_HI
 
 }  // namespace ra

@@ -10,13 +10,51 @@ struct PlanArgs {
     int buckets;      // 1: single bucket (plain), kBuckets: LPT buckets
     int extend;
     PlanScratch s;
+    const int32_t *band;   // banded planning (band half-width per pair), else null
 };
+
+// Banded pairs (dtw_band.hip): class 0 for frames of at most kBandLoMaxH*128
+// columns, class 1 for wider ones, longest first by the frame cells swept.
+// Pairs that need no kernel get their result here: NaN/-2 for an invalid
+// slice or a negative band, (0, -1) for an empty query, (+inf, -1) for an
+// empty region, NaN/-4 for a shape the banded kernel does not take (more
+// levels than events, or a band wider than one wave's frame).
+RA_DEV int band_classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
+    const PairArrays &a = pa.a;
+    const int n = a.q_len[p];
+    const int m = a.r_len[p];
+    const int wraw = pa.band[p];
+    if (!slices_ok(a, p, false) || wraw < 0) {
+        score = __builtin_nanf("");
+        end = -2;
+        return -1;
+    }
+    if (n == 0 || m == 0) {
+        score = n == 0 ? 0.0f : kInf;
+        end = -1;
+        return -1;
+    }
+    const int w = wraw < m - 1 ? wraw : m - 1;
+    const int W = 2 * w + 1;
+    if (m > n || W > kBandMaxFrame) {
+        score = __builtin_nanf("");
+        end = -4;
+        return -1;
+    }
+    const int h = (W + 127) / 128;
+    const float work = (float)(n + 64) * (float)(128 * h) + 1.0f;
+    int b = (int)(4.0f * __log2f(work));
+    b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
+    bucket = kBuckets - 1 - b;
+    return h <= kBandLoMaxH ? 0 : 1;
+}
 
 // Route of pair p.  Returns -1 when the pair needs no kernel; then
 // (score, end) is its result: a sentinel for invalid slices (NaN, -2) or the
 // value of a degenerate pair (empty query or empty region).  Returns -2 for
 // a global pair that the one-pair-per-lane kernel aligns (no output here).
 RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
+    if (pa.band) return band_classify(pa, p, bucket, score, end);
     const PairArrays &a = pa.a;
     const int n = a.q_len[p];
     const int m = a.r_len[p];
@@ -163,6 +201,18 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_scatter(PlanArgs pa) {
     }
 }
 
+static hipError_t run_plan(const PlanArgs &pa, hipStream_t stream) {
+    const PlanScratch &s = pa.s;
+    const int64_t n_pairs = pa.n_pairs;
+    hipLaunchKernelGGL(k_plan_zero, dim3((kBins + 255) / 256), dim3(256), 0, stream, s);
+    const int64_t g64 = (n_pairs + kPlanBlock - 1) / kPlanBlock;
+    const unsigned g = (unsigned)(g64 < kPlanGrid ? g64 : kPlanGrid);
+    hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(kPlanBlock), 0, stream, pa);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
+    hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(kPlanBlock), 0, stream, pa);
+    return hipGetLastError();
+}
+
 hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg, const PlanScratch &s,
                        hipStream_t stream) {
     PlanArgs pa;
@@ -171,13 +221,20 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
     pa.buckets = cfg.persistent ? kBuckets : 1;
     pa.extend = a.rows != nullptr;
     pa.s = s;
-    hipLaunchKernelGGL(k_plan_zero, dim3((kBins + 255) / 256), dim3(256), 0, stream, s);
-    const int64_t g64 = (n_pairs + kPlanBlock - 1) / kPlanBlock;
-    const unsigned g = (unsigned)(g64 < kPlanGrid ? g64 : kPlanGrid);
-    hipLaunchKernelGGL(k_plan_count, dim3(g), dim3(kPlanBlock), 0, stream, pa);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(64), 0, stream, s);
-    hipLaunchKernelGGL(k_plan_scatter, dim3(g), dim3(kPlanBlock), 0, stream, pa);
-    return hipGetLastError();
+    pa.band = nullptr;
+    return run_plan(pa, stream);
+}
+
+hipError_t launch_band_plan(const PairArrays &a, const int32_t *band, int64_t n_pairs, const PlanScratch &s,
+                            hipStream_t stream) {
+    PlanArgs pa;
+    pa.a = a;
+    pa.n_pairs = n_pairs;
+    pa.buckets = kBuckets;
+    pa.extend = 0;
+    pa.s = s;
+    pa.band = band;
+    return run_plan(pa, stream);
 }
 
 // ---- alignment start -------------------------------------------------------------

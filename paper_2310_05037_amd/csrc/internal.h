@@ -176,11 +176,17 @@ hipError_t launch_tiny(const PairArrays &a, int64_t n_pairs, const TinyScratch &
 hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_len, hipStream_t stream);
 hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_t n_pairs, int32_t *out_start,
                               hipStream_t stream);
-// Banded subsequence DTW: one wave per pair, pairs taken from `queue`
-// (zeroed by the launch) in arrival order.
-hipError_t launch_band(const PairArrays &a, const int32_t *band, int64_t n_pairs, int grid, int32_t *queue,
+// Banded subsequence DTW, one wave per pair.  The planner (same scratch and
+// kernels as the striped routes) gives every pair a band class and writes
+// the sentinels of the pairs that need no kernel; each class kernel then
+// takes its list longest first from its persistent queue.
+constexpr int kBandMaxFrame = 64 * 32;   // band columns one wave takes (C <= 32 per lane)
+constexpr int kBandLoMaxH = 4;           // class 0: frames of at most 4*128 columns (C <= 8)
+hipError_t launch_band_plan(const PairArrays &a, const int32_t *band, int64_t n_pairs, const PlanScratch &s,
+                            hipStream_t stream);
+hipError_t launch_band(int cls, const PairArrays &a, const int32_t *band, int grid, const PlanScratch &s,
                        hipStream_t stream);
-int band_blocks_per_cu();
+int band_blocks_per_cu(int cls);
 hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t *chain_gap_off,
                             const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
                             hipStream_t stream);

@@ -724,7 +724,7 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
     rc = device_info(dev, info);
     if (rc) return rc;
     StreamScratch *s = nullptr;
-    rc = get_scratch(dev, c.stream, 0, 0, 0, false, false, s);
+    rc = get_scratch(dev, c.stream, n_pairs, 0, 0, false, true, s);
     if (rc) return rc;
     ra::PairArrays a;
     a.q = q;
@@ -741,9 +741,23 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
     a.rows_size = 0;
     a.row_off = nullptr;
     a.first_chunk = nullptr;
-    const int grid = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(), n_pairs);
-    hipError_t e = ra::launch_band(a, band, n_pairs, grid, plan_view(*s).queue, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "banded kernel");
+    a.bound = ra::kBoundSubseq;
+    a.reverse = 0;
+    const ra::PlanScratch ps = plan_view(*s);
+    hipError_t e = ra::launch_band_plan(a, band, n_pairs, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "banded planning");
+    // The two band classes run concurrently on internal streams joined back
+    // to the caller's stream.
+    if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int cls = 0; cls < 2; ++cls) {
+        if ((e = hipStreamWaitEvent(s->sub[cls], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        const int grid = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(cls), n_pairs);
+        e = ra::launch_band(cls, a, band, grid, ps, s->sub[cls]);
+        if (e != hipSuccess) return hip_fail(e, "banded kernel");
+        if ((e = hipEventRecord(s->join[cls], s->sub[cls])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipStreamWaitEvent(c.stream, s->join[cls], 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent");
+    }
     return RAWALIGN_OK;
 }
 
