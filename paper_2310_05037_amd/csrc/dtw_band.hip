@@ -69,19 +69,26 @@ RA_DEV float level_raw(__amdgpu_buffer_rsrc_t rs, int j, int m) {
 }
 
 // Forces the previous-row value at frame position W (lane kk, register vk)
-// to +inf.  vk is uniform: the register is picked by an indexed move on a
-// vector value (a switch over vk gets merged into one indexed store, which
-// sends the arrays to scratch memory).
+// to +inf.  W is odd and C even, so vk is odd (0 means no kill).  Up to 8
+// columns per lane, one select per odd register; wider lanes pick the
+// register by an indexed move on a vector value (vk is uniform).  A switch
+// over vk would be merged into one indexed store and send the arrays to
+// scratch memory.
 template <int C>
 RA_DEV void kill_slot(float (&An)[C], int vk, bool mine) {
-    typedef float vec_t __attribute__((ext_vector_type(C)));
-    vec_t x;
+    if constexpr (C <= 8) {
 #pragma unroll
-    for (int v = 0; v < C; ++v) x[v] = An[v];
-    const float cur = x[vk];
-    x[vk] = mine ? kInf : cur;
+        for (int v = 1; v < C; v += 2) An[v] = (mine && vk == v) ? kInf : An[v];
+    } else {
+        typedef float vec_t __attribute__((ext_vector_type(C)));
+        vec_t x;
 #pragma unroll
-    for (int v = 0; v < C; ++v) An[v] = x[v];
+        for (int v = 0; v < C; ++v) x[v] = An[v];
+        const float cur = x[vk];
+        x[vk] = mine ? kInf : cur;
+#pragma unroll
+        for (int v = 0; v < C; ++v) An[v] = x[v];
+    }
 }
 
 // One step: row i of this lane (frame shift sh) from Ao to An.
