@@ -320,6 +320,12 @@ def banded_leg(lib, valu_peak: float, opts=None, steps: int = 5, warmup: int = 1
         return e0.elapsed_time(e1) / steps
     band_ms = timed(run_band)
     end = db.end.cpu().numpy()
+    # the same pairs with bands of 5% and 10% of the segment on each side
+    narrow_ms = {}
+    for frac in (0.05, 0.10):
+        nb = torch.from_numpy(np.ceil(frac * b.r_len).astype(np.int32)).to(db.q.device)
+        narrow_ms[frac] = timed(lambda: lib.rawalign_dtw_band(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len,
+                                                              nb, db.score, db.end, stream=stream))
     full_ms = timed(lambda: db.run(opts=opts, stream=stream))
     n = b.q_len.astype(np.int64)
     m = b.r_len.astype(np.int64)
@@ -339,6 +345,8 @@ def banded_leg(lib, valu_peak: float, opts=None, steps: int = 5, warmup: int = 1
             "full_table_cells": b.cells, "frame_cells": frame_cells,
             "band_gcups": band_cells / (band_ms / 1e3) / 1e9, "full_table_gcups": b.cells / (full_ms / 1e3) / 1e9,
             "speedup_over_full_table": full_ms / band_ms, "unsupported_pairs": int((end == -4).sum()),
+            "band_10pct_ms": narrow_ms[0.10], "band_10pct_speedup_over_full_table": full_ms / narrow_ms[0.10],
+            "band_5pct_ms": narrow_ms[0.05], "band_5pct_speedup_over_full_table": full_ms / narrow_ms[0.05],
             "roofline": {"bound": "alu", "achieved": ops / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
                          "frac": ops / valu_peak, "over": "band cells at 3 VALU each"},
             "entry_point": "rawalign_dtw_band", "workload": "chained_segments_100000"}

@@ -134,3 +134,28 @@ def test_band_chained_segments(L):
     b, band = W.chained_segments(ab)
     s, e = _gpu_band(L, b, band)
     _check(b, band, s, e)
+
+
+def test_band_chained_segments_full_size_sampled(L):
+    """The 100,000 chained segments of the banded benchmark in one call (the
+    launch the benchmark times): on a sample stratified by frame width (every
+    columns-per-lane class) plus random pairs, scores and ends bit for bit
+    against the float oracle; every pair with more levels than events carries
+    the -4 sentinel and no other does."""
+    ab = W.anchored_chains()
+    b, band = W.chained_segments(ab)
+    s, e = _gpu_band(L, b, band)
+    m = b.r_len.astype(np.int64)
+    n = b.q_len.astype(np.int64)
+    w = np.minimum(band.astype(np.int64), m - 1)
+    h = (2 * w + 1 + 127) // 128
+    rng = np.random.default_rng(2024)
+    pick = [rng.choice(np.flatnonzero(h == k), size=min(12, int((h == k).sum())), replace=False)
+            for k in np.unique(h)]
+    pick.append(rng.choice(b.n_pairs, size=120, replace=False))
+    pairs = np.unique(np.concatenate(pick))
+    _check(b, band, s, e, pairs)
+    assert np.array_equal(np.flatnonzero(e == -4), np.flatnonzero(m > n))
+    ok = e >= 0
+    assert ok.sum() == b.n_pairs - int((m > n).sum())
+    assert np.all(np.isfinite(s[ok]))
