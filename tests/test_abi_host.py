@@ -131,3 +131,17 @@ def test_binding_rejects_host_tensors(L):
     t = torch.zeros(4)
     with pytest.raises(TypeError):
         L._dev(t, torch.float32, "q")
+
+
+def test_band_argument_errors_without_device(L):
+    so = L.load()
+    fake = ctypes.c_void_p(0x1000)
+    # the band array is required, the end output too; zero pairs is a no-op
+    rc = so.rawalign_dtw_band(fake, 10, fake, fake, fake, 10, fake, fake, None, 2, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"band" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_band(fake, 10, fake, fake, fake, 10, fake, fake, fake, -1, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_band(fake, 10, None, fake, fake, 10, fake, fake, fake, 2, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"null" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_band(None, 0, None, None, None, 0, None, None, None, 0, None, None, None)
+    assert rc == L.RAWALIGN_OK
