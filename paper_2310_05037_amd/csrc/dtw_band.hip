@@ -94,11 +94,12 @@ RA_DEV void kill_slot(float (&An)[C], int vk, bool mine) {
 // One step: row i of this lane (frame shift sh) from Ao to An.
 //   qv: the row's event; el: west value of position 0 (row i); ed: the west
 //   value of the previous step (row i-1, frame i-1); r63: lane 63's new
-//   level when its frame moves; kill_x: this lane must treat its incoming
-//   north value as +inf (position W is lane k+1's first position).
+//   level when its frame moves; xd: carries lane k+1's first position into
+//   lane k (lane 63 holds +inf: past the frame).
 template <int C, bool MASKED>
-RA_DEV void band_step(bool valid, bool sh, float qv, float el, float ed, float r63, bool kill_x, int kill_v,
+RA_DEV void band_step(bool valid, bool sh, float qv, float el, float ed, float r63, float &xd, int kill_v,
                       bool kill_mine, float (&rv)[C], const float (&Ao)[C], float (&An)[C]) {
+    static_assert(C % 2 == 0, "W is odd and C even: position W is never a lane's first position");
     // levels of this row's frame
     const float r0 = sh ? rv[1] : rv[0];
     const float xr = dpp_shl1(r63, r0);
@@ -109,8 +110,7 @@ RA_DEV void band_step(bool valid, bool sh, float qv, float el, float ed, float r
     const float ud = sh ? Ao[0] : ed;
     float up = sh ? Ao[1] : Ao[0];
     float prev = fabsf(qv - rv[0]) + fminf(fminf(ud, up), el);
-    float xd = dpp_shl1(kInf, prev);
-    xd = kill_x ? kInf : xd;
+    xd = dpp_shl1(xd, prev);
     An[0] = (MASKED && !valid) ? Ao[0] : prev;
 #pragma unroll
     for (int v = 1; v < C; ++v) {
@@ -139,23 +139,23 @@ RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
         A[v] = 0.0f;
         B[v] = 0.0f;
     }
-    // Position W: static kill of the incoming value when it is a lane's
-    // first position, else a register of lane W / C.
+    // Position W: register W % C (odd) of lane W / C, if inside the frame.
     const int F = 64 * C;
     const bool has_kill = W < F;
     const int kk = W / C, kv = W % C;
-    const bool kill_x = has_kill && kv == 0 && lane == kk - 1;
-    const int kill_v = has_kill && kv != 0 ? kv : 0;   // 0: no register kill
+    const int kill_v = has_kill ? kv : 0;   // 0: no register kill
     const bool kill_mine = lane == kk;
     // Uniform counters: lane 0's row t (shift injected at step t) and lane
     // 63's row t - 63 + 2 (its new level, loaded two steps ahead).
     RowCounter c0{0, 0}, c63{0, 0};
     int row63 = -61;   // row of c63
     const int nm1 = n - 1;
-    // el: west value of position 0 from the previous step.  Its initial 0 is
-    // row -1 (free start): lane 0's north-west value at row 0; later lane 0
-    // injects +inf (west of the band).
-    float qv = 0.0f, el = 0.0f;
+    // ela, elb: west value of position 0 at even and odd steps.  elb starts
+    // at 0: row -1 (free start) is lane 0's north-west value at row 0.  Lane
+    // 0 injects +inf (west of the band); once both registers hold it there,
+    // the unmasked steps shift into them in place.  xd likewise keeps +inf
+    // in lane 63.
+    float qv = 0.0f, ela = 0.0f, elb = 0.0f, xd = kInf;
     int sv = 0;
     float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
     float ra = kInf, rb = kInf;   // lane 63's new levels for steps t, t+1
@@ -192,22 +192,22 @@ RA_DEV void band_pair(const BandView &bv, float &best, int &bj) {
         {                                                                                     \
             qv = dpp_shr1(q0, qv);                                                            \
             sv = dpp_shr1_i(s0, sv);                                                          \
-            const float eprev = el;                                                           \
-            el = dpp_shr1(kInf, A[C - 1]);                                                    \
-            const bool valid = (unsigned)(t - lane) < (unsigned)n;                            \
-            band_step<C, MASKED>(valid, valid && sv != 0, qv, el, eprev, r0v, kill_x, kill_v, \
+            ela = dpp_shr1(MASKED ? kInf : ela, A[C - 1]);                                    \
+            const bool valid = !MASKED || (unsigned)(t - lane) < (unsigned)n;                 \
+            band_step<C, MASKED>(valid, valid && sv != 0, qv, ela, elb, r0v, xd, kill_v,      \
                                  kill_mine, rv, A, B);                                        \
         }                                                                                     \
         {                                                                                     \
             qv = dpp_shr1(q1, qv);                                                            \
             sv = dpp_shr1_i(s1, sv);                                                          \
-            const float eprev = el;                                                           \
-            el = dpp_shr1(kInf, B[C - 1]);                                                    \
-            const bool valid = (unsigned)(t + 1 - lane) < (unsigned)n;                        \
-            band_step<C, MASKED>(valid, valid && sv != 0, qv, el, eprev, r1v, kill_x, kill_v, \
+            elb = dpp_shr1(MASKED ? kInf : elb, B[C - 1]);                                    \
+            const bool valid = !MASKED || (unsigned)(t + 1 - lane) < (unsigned)n;             \
+            band_step<C, MASKED>(valid, valid && sv != 0, qv, elb, ela, r1v, xd, kill_v,      \
                                  kill_mine, rv, B, A);                                        \
         }                                                                                     \
     }
+    // Fill (t < 64), then steps at which every lane's row is in [0, n)
+    // (rows t - 63 >= 1 and t + 1 <= n - 1), then drain.
     for (; t < ta; t += 2) RA_BAND_STEPS(true)
     for (; t < tb; t += 2) RA_BAND_STEPS(false)
     for (; t < T; t += 2) RA_BAND_STEPS(true)
