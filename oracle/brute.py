@@ -158,3 +158,48 @@ def brute_band(q, r, w):
             if i2 < n and j2 < m and ok(i2, j2):
                 stack.append((i2, j2, acc + abs(q[i2] - r[j2])))
     return best, best_end
+
+
+def brute_path(q, r, start, end):
+    """The warping path that the tie rule of the path oracle selects, by
+    explicit enumeration: among all paths from (0, start) to (n-1, end)
+    whose cost (summed in double, path order) is the smallest, the one whose
+    moves read backwards from (n-1, end) are first in the order north-west <
+    north < west.  Returns (cost, lo, hi) with lo[i] .. hi[i] the columns of
+    row i.  Use exactly representable inputs, so that equal costs are equal
+    in double."""
+    q = [float(x) for x in q]
+    r = [float(x) for x in r]
+    n = len(q)
+    best = None
+    # Paths walked backwards from (n-1, end): each step is NW (0), N (1), W (2).
+    stack = [((n - 1, end), abs(q[n - 1] - r[end]), ())]
+    while stack:
+        (i, j), acc, moves = stack.pop()
+        if i == 0 and j == start:
+            key = (acc, moves)
+            if best is None or key < best:
+                best = key
+            continue
+        if i > 0 and j > start:
+            stack.append(((i - 1, j - 1), acc + abs(q[i - 1] - r[j - 1]), moves + (0,)))
+        if i > 0:
+            stack.append(((i - 1, j), acc + abs(q[i - 1] - r[j]), moves + (1,)))
+        if j > start:
+            stack.append(((i, j - 1), acc + abs(q[i] - r[j - 1]), moves + (2,)))
+    cost, moves = best
+    lo = [0] * n
+    hi = [0] * n
+    i, j = n - 1, end
+    hi[i] = j
+    lo[i] = j
+    for mv in moves:
+        if mv == 2:
+            j -= 1
+        else:
+            if mv == 0:
+                j -= 1
+            i -= 1
+            hi[i] = j
+        lo[i] = j
+    return cost, lo, hi

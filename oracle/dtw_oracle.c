@@ -375,6 +375,117 @@ static int32_t rev_argmin_f32(const float *q, int64_t n, const float *r, int32_t
     return arg;
 }
 
+/*
+ * The warping path of an alignment (Sec. 2.4: the path can be added to the
+ * output).  Given the alignment's start s and end e (oracle_dtw_span_*), the
+ * path is an optimal global path from (0, s) to (n-1, e): global DTW of the
+ * whole query against r[s..e], entered from the corner D(-1, s-1) = 0 and
+ * left at (n-1, e).  Every cell records which neighbour gave its minimum,
+ * preferring the north-west one, then the north, then the west on ties, and
+ * the path is read back from (n-1, e).  A monotone path covers a contiguous
+ * column range in every row: lo[i] .. hi[i] (region indices) are the levels
+ * that read event i is aligned with.  Returns the path's cost (the global
+ * cost of [s, e]); NAN if memory runs out.
+ */
+#define PATH_NW 0
+#define PATH_N 1
+#define PATH_W 2
+
+static void path_trace(const unsigned char *dir, int64_t n, int64_t L, int32_t s, int32_t *lo, int32_t *hi)
+{
+    int64_t i = n - 1, j = L - 1;
+    hi[i] = (int32_t)(s + j);
+    for (;;) {
+        lo[i] = (int32_t)(s + j);
+        if (i == 0 && j == 0)
+            break;
+        unsigned char d = dir[i * L + j];
+        if (d == PATH_W) {
+            --j;
+        } else {
+            if (d == PATH_NW)
+                --j;
+            --i;
+            hi[i] = (int32_t)(s + j);
+        }
+    }
+}
+
+double oracle_dtw_path_f64(const float *q, int64_t n, const float *r, int32_t s, int32_t e, int32_t *lo,
+                           int32_t *hi)
+{
+    int64_t L = (int64_t)e - s + 1;
+    double *prev = malloc((size_t)(L + 1) * sizeof(double));
+    double *cur = malloc((size_t)(L + 1) * sizeof(double));
+    unsigned char *dir = malloc((size_t)(n * L));
+    if (!prev || !cur || !dir) {
+        free(prev);
+        free(cur);
+        free(dir);
+        return NAN;
+    }
+    prev[0] = 0.0; /* the corner D(-1, s-1) */
+    for (int64_t j = 0; j < L; ++j)
+        prev[j + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        double qi = (double)q[i];
+        for (int64_t j = 0; j < L; ++j) {
+            double nw = prev[j], no = prev[j + 1], we = cur[j];
+            double mn = min3_d(nw, no, we);
+            dir[i * L + j] = nw == mn ? PATH_NW : (no == mn ? PATH_N : PATH_W);
+            cur[j + 1] = fabs(qi - (double)r[s + j]) + mn;
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    double g = prev[L];
+    path_trace(dir, n, L, s, lo, hi);
+    free(prev);
+    free(cur);
+    free(dir);
+    return g;
+}
+
+float oracle_dtw_path_f32(const float *q, int64_t n, const float *r, int32_t s, int32_t e, int32_t *lo,
+                          int32_t *hi)
+{
+    int64_t L = (int64_t)e - s + 1;
+    float *prev = malloc((size_t)(L + 1) * sizeof(float));
+    float *cur = malloc((size_t)(L + 1) * sizeof(float));
+    unsigned char *dir = malloc((size_t)(n * L));
+    if (!prev || !cur || !dir) {
+        free(prev);
+        free(cur);
+        free(dir);
+        return NAN;
+    }
+    prev[0] = 0.0f;
+    for (int64_t j = 0; j < L; ++j)
+        prev[j + 1] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        cur[0] = INFINITY;
+        float qi = q[i];
+        for (int64_t j = 0; j < L; ++j) {
+            float nw = prev[j], no = prev[j + 1], we = cur[j];
+            float mn = min3_f(nw, no, we);
+            dir[i * L + j] = nw == mn ? PATH_NW : (no == mn ? PATH_N : PATH_W);
+            float d = qi - r[s + j];
+            cur[j + 1] = fabsf(d) + mn;
+        }
+        float *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    float g = prev[L];
+    path_trace(dir, n, L, s, lo, hi);
+    free(prev);
+    free(cur);
+    free(dir);
+    return g;
+}
+
 /* Subsequence DTW with its start: returns C_DTW, writes end and start. */
 double oracle_dtw_span_f64(const float *q, int64_t n, const float *r, int64_t m, int32_t *end, int32_t *start)
 {

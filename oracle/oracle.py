@@ -90,6 +90,10 @@ def lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = [f32p, i64p, i32p, f32p, i64p, i32p, i64, outp, i32p, i32p, ctypes.c_int]
+        L.oracle_dtw_path_f64.restype = ctypes.c_double
+        L.oracle_dtw_path_f64.argtypes = [f32p, i64, f32p, ctypes.c_int32, ctypes.c_int32, i32p, i32p]
+        L.oracle_dtw_path_f32.restype = ctypes.c_float
+        L.oracle_dtw_path_f32.argtypes = [f32p, i64, f32p, ctypes.c_int32, ctypes.c_int32, i32p, i32p]
         L.oracle_dtw_global_f64.restype = ctypes.c_double
         L.oracle_dtw_global_f64.argtypes = [f32p, i64, f32p, i64]
         L.oracle_dtw_global_f32.restype = ctypes.c_float
@@ -329,6 +333,35 @@ def dtw_span_f32(q, r):
     c = lib().oracle_dtw_span_f32(_ptr(q, ctypes.c_float), len(q), _ptr(r, ctypes.c_float), len(r),
                                   ctypes.byref(e), ctypes.byref(st))
     return np.float32(c), e.value, st.value
+
+
+def _path(fn, span, cast, q, r):
+    q = _f32(q)
+    r = _f32(r)
+    c, e, st = span(q, r)
+    n = len(q)
+    lo = np.full(n, -1, dtype=np.int32)
+    hi = np.full(n, -1, dtype=np.int32)
+    if e < 0:
+        return c, e, st, cast(np.nan if e < -1 else c), lo, hi
+    g = fn(_ptr(q, ctypes.c_float), n, _ptr(r, ctypes.c_float), st, e, _ptr(lo, ctypes.c_int32),
+           _ptr(hi, ctypes.c_int32))
+    return c, e, st, cast(g), lo, hi
+
+
+def dtw_path_f64(q, r):
+    """Subsequence DTW with its warping path, double precision (Sec. 2.4):
+    (C_DTW, end, start, path cost, lo, hi) where read event i is aligned with
+    region levels lo[i] .. hi[i] on an optimal path from (0, start) to
+    (n-1, end); the path cost is the global cost of [start, end].  Empty
+    query or region: lo = hi = -1."""
+    return _path(lib().oracle_dtw_path_f64, dtw_span_f64, float, q, r)
+
+
+def dtw_path_f32(q, r):
+    """The same with every value in float (start from the float reverse
+    pass, path from the float table)."""
+    return _path(lib().oracle_dtw_path_f32, dtw_span_f32, np.float32, q, r)
 
 
 def _span_batch(fn, dtype, q, q_off, q_len, r, r_off, r_len, threads):
