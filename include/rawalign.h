@@ -244,6 +244,38 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
                       const rawalign_opts *opts);
 
 /*
+ * Subsequence DTW with the warping path of every alignment (Sec. 2.4: the
+ * alignment path as an optional output).  First as rawalign_dtw_span (score,
+ * end e, start s); then the path is an optimal global path from (0, s) to
+ * (n-1, e), i.e. global DTW of the whole query against r[s..e] entered from
+ * the corner D(-1, s-1) = 0, with ties between the neighbours resolved
+ * north-west first, then north, then west when the path is read back from
+ * (n-1, e).  A monotone path covers a contiguous range of every row:
+ *   path_off   device int64 per pair: offset of the pair's n entries in
+ *              path_lo / path_hi (caller-owned, path_size entries each)
+ *   path_lo[path_off[p] + i], path_hi[path_off[p] + i]
+ *              the first and last region columns that read event i is
+ *              aligned with (region indices, like end and start):
+ *              path_lo[off] = start, path_hi[off + n - 1] = end.
+ *   max_query  the path is recorded for pairs of at most max_query events
+ *              whose interval [s, e] spans at most 2048 levels; the others
+ *              get -4 in every entry.  Pairs without an alignment get their
+ *              end sentinel in every entry (-1 empty region, -2 invalid
+ *              slice); an empty query has no entries.  Entries of a pair
+ *              whose range leaves [0, path_size) are not written.
+ *   Other arguments, opts and errors as in rawalign_dtw_span.  Scratch: that
+ *   of rawalign_dtw_span plus n_pairs * max_query * 512 bytes of direction
+ *   words (2 bits per cell), per (device, stream), kept for later calls.
+ *   One wave per pair records the directions in the lane-striped order of
+ *   the other kernels; one thread per pair then follows them back.
+ */
+int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, int32_t max_query, const int64_t *path_off, int32_t *path_lo,
+                      int32_t *path_hi, int64_t path_size, float *out_score, int32_t *out_end,
+                      int32_t *out_start, void *stream, const rawalign_opts *opts);
+
+/*
  * Banded subsequence DTW (Sec. 2.4.3): only the cells near the diagonal of
  * slope n/m are computed.  Row i's diagonal column is c(i) = floor(i*m/n);
  * cell (i, j) is in the band iff |j - c(i)| <= band[p] (half-width in

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "dtw_path.h"
 #include "internal.h"
 #include "rawalign.h"
 
@@ -78,6 +79,13 @@ struct SpanStore {
     int64_t pairs = 0;
 };
 std::map<std::pair<int, hipStream_t>, SpanStore> g_span;
+
+// Direction words of the path pass, per (device, stream), grown on demand.
+struct PathStore {
+    void *mem = nullptr;
+    size_t bytes = 0;
+};
+std::map<std::pair<int, hipStream_t>, PathStore> g_path;
 
 struct TimingRecord {
     hipEvent_t ev[8] = {};
@@ -707,6 +715,66 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
     if (rc) return rc;
     e = ra::launch_span_finish(out_end, rev_end, n_pairs, out_start, st);
     if (e != hipSuccess) return hip_fail(e, "span kernels");
+    return RAWALIGN_OK;
+}
+
+int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                      const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                      int64_t n_pairs, int32_t max_query, const int64_t *path_off, int32_t *path_lo,
+                      int32_t *path_hi, int64_t path_size, float *out_score, int32_t *out_end,
+                      int32_t *out_start, void *stream, const rawalign_opts *opts) {
+    if (max_query < 0) return fail(RAWALIGN_EINVAL, "max_query must be >= 0");
+    if (path_size < 0) return fail(RAWALIGN_EINVAL, "path_size must be >= 0");
+    if (n_pairs > 0 && (!path_off || !path_lo || !path_hi))
+        return fail(RAWALIGN_EINVAL, "null pointer argument: path_off, path_lo and path_hi are required");
+    int rc = rawalign_dtw_span(q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+                               out_start, stream, opts);
+    if (rc || n_pairs == 0) return rc;
+    int dev = 0;
+    DeviceInfo info;
+    rc = device_info(dev, info);
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    if ((double)n_pairs * (double)max_query * ra::kPathWordsPerRow * sizeof(uint64_t) > (double)((int64_t)1 << 46))
+        return fail(RAWALIGN_ENOMEM, "path directions: n_pairs * max_query * 512 bytes exceeds 64 TiB");
+    const size_t bytes = (size_t)n_pairs * (size_t)max_query * ra::kPathWordsPerRow * sizeof(uint64_t);
+    void *dirs = nullptr;
+    if (bytes) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        PathStore &ps = g_path[{dev, st}];
+        if (ps.bytes < bytes) {
+            if (ps.mem) (void)hipFree(ps.mem);
+            ps.mem = nullptr;
+            ps.bytes = 0;
+            hipError_t e = hipMalloc(&ps.mem, bytes);
+            if (e != hipSuccess) {
+                ps.mem = nullptr;
+                return alloc_fail(e);
+            }
+            ps.bytes = bytes;
+        }
+        dirs = ps.mem;
+    }
+    ra::PathArgs pa;
+    pa.q = q;
+    pa.q_size = q_size;
+    pa.q_off = q_off;
+    pa.q_len = q_len;
+    pa.r = r;
+    pa.r_size = r_size;
+    pa.r_off = r_off;
+    pa.r_len = r_len;
+    pa.start = out_start;
+    pa.end = out_end;
+    pa.n_pairs = n_pairs;
+    pa.max_query = max_query;
+    pa.dirs = (uint64_t *)dirs;
+    pa.path_off = path_off;
+    pa.path_lo = path_lo;
+    pa.path_hi = path_hi;
+    pa.path_size = path_size;
+    hipError_t e = ra::launch_path(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "path kernels");
     return RAWALIGN_OK;
 }
 

@@ -32,7 +32,8 @@ FLAG_TIMING = 1
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
     "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
-    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_band", "rawalign_dtw_global_batch",
+    "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_path", "rawalign_dtw_band",
+    "rawalign_dtw_global_batch",
     "rawalign_chain_decide",
     "rawalign_autotune", "rawalign_load_tuning", "rawalign_last_timing", "rawalign_last_error", "rawalign_version",
 )
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
                                    vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_dtw_global_batch.argtypes = pair_args + [ctypes.POINTER(Opts)]
     L.rawalign_dtw_span.argtypes = pair_args[:11] + [vp, vp, ctypes.POINTER(Opts)]
+    L.rawalign_dtw_path.argtypes = pair_args[:9] + [i32, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_dtw_band.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.rawalign_chain_decide.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
@@ -224,6 +226,22 @@ def rawalign_dtw_span(q, q_off, q_len, r, r_off, r_len, out_score, out_end, out_
         raise ValueError(f"out_start has {out_start.numel()} elements, expected {a[8]}")
     _check(load().rawalign_dtw_span(*a, _dev(out_start, torch.int32, "out_start"), _stream(stream),
                                     None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_dtw_path(q, q_off, q_len, r, r_off, r_len, max_query, path_off, path_lo, path_hi, out_score, out_end,
+                      out_start, opts=None, stream=None):
+    import torch
+    a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
+    n = a[8]
+    for t, nm in ((path_off, "path_off"), (out_start, "out_start")):
+        if t.numel() != n:
+            raise ValueError(f"{nm} has {t.numel()} elements, expected {n}")
+    if path_lo.numel() != path_hi.numel():
+        raise ValueError("path_lo and path_hi must have the same size")
+    _check(load().rawalign_dtw_path(*a[:9], int(max_query), _dev(path_off, torch.int64, "path_off"),
+                                    _dev(path_lo, torch.int32, "path_lo"), _dev(path_hi, torch.int32, "path_hi"),
+                                    path_lo.numel(), a[9], a[10], _dev(out_start, torch.int32, "out_start"),
+                                    _stream(stream), None if opts is None else ctypes.byref(opts)))
 
 
 def rawalign_dtw_band(q, q_off, q_len, r, r_off, r_len, band, out_score, out_end, stream=None):
