@@ -289,6 +289,51 @@ def span_leg(lib, db, opts, steps: int = 3):
             "mean_span_levels": float(np.mean(end - st + 1)), "entry_point": "rawalign_dtw_span"}
 
 
+def path_leg(lib, b, opts, steps: int = 3):
+    """Warping paths (Sec. 2.4) of the true candidate of every read of the
+    uneven batch (3,901 pairs, the ones a mapper would report):
+    rawalign_dtw_path (forward and reverse passes, direction words, trace
+    back) against rawalign_dtw_span alone on the same pairs."""
+    import torch
+    tp = b.true_pair[b.true_pair >= 0]
+    sub = b.subset(tp)
+    db = lib.DeviceBatch(sub)
+    n = sub.n_pairs
+    rows = sub.q_len.astype(np.int64)
+    path_off = torch.from_numpy(np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)).cuda()
+    lo = torch.empty(int(rows.sum()), dtype=torch.int32, device="cuda")
+    hi = torch.empty_like(lo)
+    start = torch.empty(n, dtype=torch.int32, device="cuda")
+    max_query = int(rows.max())
+
+    def path():
+        lib.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, max_query, path_off, lo, hi,
+                              db.score, db.end, start, opts=opts)
+
+    def span():
+        lib.rawalign_dtw_span(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, db.score, db.end, start,
+                              opts=opts)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+    span_ms = timed(span)
+    path_ms = timed(path)
+    l0 = lo[path_off].cpu().numpy()
+    end = db.end.cpu().numpy().astype(np.int64)
+    st = start.cpu().numpy().astype(np.int64)
+    rec = l0 >= 0
+    return {"ms_per_batch": path_ms, "span_only_ms": span_ms, "pairs": n, "paths_recorded": int(rec.sum()),
+            "mean_interval_levels": float(np.mean((end - st + 1)[rec])),
+            "direction_bytes": int((rows[rec] * 512).sum()), "max_query": max_query,
+            "entry_point": "rawalign_dtw_path", "workload": "uneven_batch_true_candidates"}
+
+
 def banded_leg(lib, valu_peak: float, opts=None, steps: int = 5, warmup: int = 1):
     """Banded DTW (Sec. 2.4.3) of whole chains: the 100,000 chained segments
     of the anchored workload (read events from the first anchor to the last
@@ -399,6 +444,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="time only the tuned path (for profiling runs)")
     ap.add_argument("--skip-anchored", action="store_true", help="leave out the anchor-guided alignment leg")
+    ap.add_argument("--only-path", action="store_true",
+                    help="run only the warping-path leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-banded", action="store_true",
                     help="run only the banded-DTW leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-anchored", action="store_true",
@@ -431,6 +478,9 @@ def main():
     valu_peak = cus * LANES_PER_CU * CLOCK_HZ
     if args.only_anchored:
         print(json.dumps({"anchored": anchored_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
+    if args.only_path:
+        print(json.dumps({"path": path_leg(lib, workloads.uneven_batch(), None, steps=args.steps)}), flush=True)
         return
     if args.only_banded:
         print(json.dumps({"banded": banded_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
@@ -489,6 +539,7 @@ def main():
     if not args.skip_plain:
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
         variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
+        variants["path"] = path_leg(lib, b, lib.make_opts(**extra))
     if not args.skip_anchored:
         variants["anchored"] = anchored_leg(lib, valu_peak)
     if not args.skip_plain:

@@ -145,3 +145,18 @@ def test_band_argument_errors_without_device(L):
     assert rc == L.RAWALIGN_EINVAL and b"null" in so.rawalign_last_error()
     rc = so.rawalign_dtw_band(None, 0, None, None, None, 0, None, None, None, 0, None, None, None)
     assert rc == L.RAWALIGN_OK
+
+
+def test_path_argument_errors_without_device(L):
+    so = L.load()
+    fake = ctypes.c_void_p(0x1000)
+
+    def path(max_query=100, path_off=fake, path_size=10, n_pairs=2, out_start=fake):
+        return so.rawalign_dtw_path(fake, 10, fake, fake, fake, 10, fake, fake, n_pairs, max_query, path_off,
+                                    fake, fake, path_size, fake, fake, out_start, None, None)
+    assert path(max_query=-1) == L.RAWALIGN_EINVAL and b"max_query" in so.rawalign_last_error()
+    assert path(path_size=-1) == L.RAWALIGN_EINVAL and b"path_size" in so.rawalign_last_error()
+    assert path(path_off=None) == L.RAWALIGN_EINVAL and b"path_off" in so.rawalign_last_error()
+    assert path(out_start=None) == L.RAWALIGN_EINVAL and b"out_start" in so.rawalign_last_error()
+    assert path(n_pairs=-1) == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
+    assert path(n_pairs=0, path_off=None) == L.RAWALIGN_OK
