@@ -304,10 +304,12 @@ def path_leg(lib, b, opts, steps: int = 3):
     lo = torch.empty(int(rows.sum()), dtype=torch.int32, device="cuda")
     hi = torch.empty_like(lo)
     start = torch.empty(n, dtype=torch.int32, device="cuda")
-    max_query = int(rows.max())
+    dir_off, words = lib.path_workspace(sub.q_len, sub.r_len)
+    dir_off = torch.from_numpy(dir_off).cuda()
+    dirs = torch.empty(words, dtype=torch.int64, device="cuda")
 
     def path():
-        lib.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, max_query, path_off, lo, hi,
+        lib.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, dir_off, dirs, path_off, lo, hi,
                               db.score, db.end, start, opts=opts)
 
     def span():
@@ -328,9 +330,11 @@ def path_leg(lib, b, opts, steps: int = 3):
     end = db.end.cpu().numpy().astype(np.int64)
     st = start.cpu().numpy().astype(np.int64)
     rec = l0 >= 0
+    L = end - st + 1
+    stripes = (L + 2047) // 2048
     return {"ms_per_batch": path_ms, "span_only_ms": span_ms, "pairs": n, "paths_recorded": int(rec.sum()),
-            "mean_interval_levels": float(np.mean((end - st + 1)[rec])),
-            "direction_bytes": int((rows[rec] * 512).sum()), "max_query": max_query,
+            "mean_interval_levels": float(np.mean(L[rec])), "max_interval_levels": int(L[rec].max()),
+            "direction_bytes": int((rows[rec] * 512 * stripes[rec]).sum()), "workspace_bytes": words * 8,
             "entry_point": "rawalign_dtw_path", "workload": "uneven_batch_true_candidates"}
 
 

@@ -257,23 +257,29 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
  *              the first and last region columns that read event i is
  *              aligned with (region indices, like end and start):
  *              path_lo[off] = start, path_hi[off + n - 1] = end.
- *   max_query  the path is recorded for pairs of at most max_query events
- *              whose interval [s, e] spans at most 2048 levels; the others
- *              get -4 in every entry.  Pairs without an alignment get their
- *              end sentinel in every entry (-1 empty region, -2 invalid
- *              slice); an empty query has no entries.  Entries of a pair
- *              whose range leaves [0, path_size) are not written.
- *   Other arguments, opts and errors as in rawalign_dtw_span.  Scratch: that
- *   of rawalign_dtw_span plus n_pairs * max_query * 512 bytes of direction
- *   words (2 bits per cell), per (device, stream), kept for later calls.
- *   One wave per pair records the directions in the lane-striped order of
- *   the other kernels; one thread per pair then follows them back.
+ *   dirs, dir_off, dir_size
+ *              caller-owned device workspace of dir_size 64-bit words; pair
+ *              p uses the words from dir_off[p] on, n * (64 * S + 1) of them
+ *              for an interval of L = e - s + 1 levels, S = ceil(L / 2048)
+ *              (2 bits per cell and a stripe edge).  The interval is at most
+ *              m levels, so n * (64 * ceil(m / 2048) + 1) words always
+ *              suffice.  A pair whose range does not hold its interval gets
+ *              -4 in every entry; pairs may share words only if they are not
+ *              both aligned in one call.
+ *   Pairs without an alignment get their end sentinel in every entry (-1
+ *   empty region, -2 invalid slice); an empty query has no entries.
+ *   Entries of a pair whose range leaves [0, path_size) are not written.
+ *   Other arguments, opts and errors as in rawalign_dtw_span; beyond that
+ *   call's scratch this entry point allocates nothing.  One wave per pair
+ *   records the directions stripe by stripe in the lane-striped order of the
+ *   other kernels; one thread per pair then follows them back.
  */
 int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
-                      int64_t n_pairs, int32_t max_query, const int64_t *path_off, int32_t *path_lo,
-                      int32_t *path_hi, int64_t path_size, float *out_score, int32_t *out_end,
-                      int32_t *out_start, void *stream, const rawalign_opts *opts);
+                      int64_t n_pairs, const int64_t *dir_off, uint64_t *dirs, int64_t dir_size,
+                      const int64_t *path_off, int32_t *path_lo, int32_t *path_hi, int64_t path_size,
+                      float *out_score, int32_t *out_end, int32_t *out_start, void *stream,
+                      const rawalign_opts *opts);
 
 /*
  * Banded subsequence DTW (Sec. 2.4.3): only the cells near the diagonal of

@@ -6,11 +6,18 @@
 
 namespace ra {
 
-// Widest interval [start, end] whose path is recorded: 64 lanes x 32 columns.
-constexpr int kPathMaxCols = 64 * 32;
-// Direction words per recorded query row: one 64-bit word (2 bits per
+// Widest stripe of the direction pass: 64 lanes x 32 columns.
+constexpr int kPathStripeCols = 64 * 32;
+// Direction words per query row and stripe: one 64-bit word (2 bits per
 // column, up to 32 columns) per lane.
 constexpr int kPathWordsPerRow = 64;
+
+// Workspace words pair p needs for an interval of L levels: per stripe and
+// row one word per lane, plus one word per row for the stripe edge.
+__host__ __device__ inline int64_t path_words(int64_t n, int64_t L) {
+    const int64_t S = (L + kPathStripeCols - 1) / kPathStripeCols;
+    return n * (kPathWordsPerRow * S + 1);
+}
 
 struct PathArgs {
     const float *q;
@@ -24,8 +31,9 @@ struct PathArgs {
     const int32_t *start;   // per pair, from the start-of-alignment pass
     const int32_t *end;
     int64_t n_pairs;
-    int max_query;          // rows of direction words per pair
-    uint64_t *dirs;         // [n_pairs][max_query][kPathWordsPerRow]
+    const int64_t *dir_off;   // per pair: first workspace word
+    uint64_t *dirs;           // caller's workspace
+    int64_t dir_size;         // words
     const int64_t *path_off;
     int32_t *path_lo;
     int32_t *path_hi;

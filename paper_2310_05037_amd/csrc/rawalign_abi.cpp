@@ -18,7 +18,7 @@
 #include "internal.h"
 #include "rawalign.h"
 
-#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.4.0"
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.5.0"
 
 namespace {
 
@@ -80,12 +80,6 @@ struct SpanStore {
 };
 std::map<std::pair<int, hipStream_t>, SpanStore> g_span;
 
-// Direction words of the path pass, per (device, stream), grown on demand.
-struct PathStore {
-    void *mem = nullptr;
-    size_t bytes = 0;
-};
-std::map<std::pair<int, hipStream_t>, PathStore> g_path;
 
 struct TimingRecord {
     hipEvent_t ev[8] = {};
@@ -720,41 +714,17 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
 
 int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
-                      int64_t n_pairs, int32_t max_query, const int64_t *path_off, int32_t *path_lo,
-                      int32_t *path_hi, int64_t path_size, float *out_score, int32_t *out_end,
-                      int32_t *out_start, void *stream, const rawalign_opts *opts) {
-    if (max_query < 0) return fail(RAWALIGN_EINVAL, "max_query must be >= 0");
-    if (path_size < 0) return fail(RAWALIGN_EINVAL, "path_size must be >= 0");
-    if (n_pairs > 0 && (!path_off || !path_lo || !path_hi))
-        return fail(RAWALIGN_EINVAL, "null pointer argument: path_off, path_lo and path_hi are required");
+                      int64_t n_pairs, const int64_t *dir_off, uint64_t *dirs, int64_t dir_size,
+                      const int64_t *path_off, int32_t *path_lo, int32_t *path_hi, int64_t path_size,
+                      float *out_score, int32_t *out_end, int32_t *out_start, void *stream,
+                      const rawalign_opts *opts) {
+    if (dir_size < 0 || path_size < 0) return fail(RAWALIGN_EINVAL, "dir_size and path_size must be >= 0");
+    if (n_pairs > 0 && (!dir_off || !path_off || !path_lo || !path_hi))
+        return fail(RAWALIGN_EINVAL, "null pointer argument: dir_off, path_off, path_lo and path_hi are required");
+    if (n_pairs > 0 && dir_size > 0 && !dirs) return fail(RAWALIGN_EINVAL, "null pointer argument: dirs");
     int rc = rawalign_dtw_span(q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
                                out_start, stream, opts);
     if (rc || n_pairs == 0) return rc;
-    int dev = 0;
-    DeviceInfo info;
-    rc = device_info(dev, info);
-    if (rc) return rc;
-    const hipStream_t st = (hipStream_t)stream;
-    if ((double)n_pairs * (double)max_query * ra::kPathWordsPerRow * sizeof(uint64_t) > (double)((int64_t)1 << 46))
-        return fail(RAWALIGN_ENOMEM, "path directions: n_pairs * max_query * 512 bytes exceeds 64 TiB");
-    const size_t bytes = (size_t)n_pairs * (size_t)max_query * ra::kPathWordsPerRow * sizeof(uint64_t);
-    void *dirs = nullptr;
-    if (bytes) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        PathStore &ps = g_path[{dev, st}];
-        if (ps.bytes < bytes) {
-            if (ps.mem) (void)hipFree(ps.mem);
-            ps.mem = nullptr;
-            ps.bytes = 0;
-            hipError_t e = hipMalloc(&ps.mem, bytes);
-            if (e != hipSuccess) {
-                ps.mem = nullptr;
-                return alloc_fail(e);
-            }
-            ps.bytes = bytes;
-        }
-        dirs = ps.mem;
-    }
     ra::PathArgs pa;
     pa.q = q;
     pa.q_size = q_size;
@@ -767,13 +737,14 @@ int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, cons
     pa.start = out_start;
     pa.end = out_end;
     pa.n_pairs = n_pairs;
-    pa.max_query = max_query;
-    pa.dirs = (uint64_t *)dirs;
+    pa.dir_off = dir_off;
+    pa.dirs = dirs;
+    pa.dir_size = dir_size;
     pa.path_off = path_off;
     pa.path_lo = path_lo;
     pa.path_hi = path_hi;
     pa.path_size = path_size;
-    hipError_t e = ra::launch_path(pa, st);
+    hipError_t e = ra::launch_path(pa, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "path kernels");
     return RAWALIGN_OK;
 }

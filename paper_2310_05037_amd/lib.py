@@ -88,7 +88,8 @@ def load(path: str = LIB_PATH):
                                    vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Opts)]
     L.rawalign_dtw_global_batch.argtypes = pair_args + [ctypes.POINTER(Opts)]
     L.rawalign_dtw_span.argtypes = pair_args[:11] + [vp, vp, ctypes.POINTER(Opts)]
-    L.rawalign_dtw_path.argtypes = pair_args[:9] + [i32, vp, vp, vp, i64, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+    L.rawalign_dtw_path.argtypes = pair_args[:9] + [vp, vp, i64, vp, vp, vp, i64, vp, vp, vp, vp,
+                                                    ctypes.POINTER(Opts)]
     L.rawalign_dtw_band.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.rawalign_chain_decide.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp]
     L.rawalign_autotune.argtypes = pair_args + [ctypes.c_char_p, ctypes.POINTER(Opts)]
@@ -228,17 +229,31 @@ def rawalign_dtw_span(q, q_off, q_len, r, r_off, r_len, out_score, out_end, out_
                                     None if opts is None else ctypes.byref(opts)))
 
 
-def rawalign_dtw_path(q, q_off, q_len, r, r_off, r_len, max_query, path_off, path_lo, path_hi, out_score, out_end,
-                      out_start, opts=None, stream=None):
+def path_workspace(q_len, r_len):
+    """(dir_off, words) of a direction workspace that holds the path of every
+    pair: n * (64 * ceil(m / 2048) + 1) 64-bit words per pair (numpy int64
+    offsets; the interval of an alignment is at most m levels)."""
+    n = np.maximum(np.asarray(q_len, dtype=np.int64), 0)
+    m = np.maximum(np.asarray(r_len, dtype=np.int64), 1)
+    words = n * (64 * ((m + 2047) // 2048) + 1)
+    off = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.int64)
+    return off, int(words.sum())
+
+
+def rawalign_dtw_path(q, q_off, q_len, r, r_off, r_len, dir_off, dirs, path_off, path_lo, path_hi, out_score,
+                      out_end, out_start, opts=None, stream=None):
+    """dirs: int64 CUDA tensor (the 64-bit direction words), dir_off: int64
+    per pair (see path_workspace)."""
     import torch
     a = _pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end)
     n = a[8]
-    for t, nm in ((path_off, "path_off"), (out_start, "out_start")):
+    for t, nm in ((dir_off, "dir_off"), (path_off, "path_off"), (out_start, "out_start")):
         if t.numel() != n:
             raise ValueError(f"{nm} has {t.numel()} elements, expected {n}")
     if path_lo.numel() != path_hi.numel():
         raise ValueError("path_lo and path_hi must have the same size")
-    _check(load().rawalign_dtw_path(*a[:9], int(max_query), _dev(path_off, torch.int64, "path_off"),
+    _check(load().rawalign_dtw_path(*a[:9], _dev(dir_off, torch.int64, "dir_off"), _dev(dirs, torch.int64, "dirs"),
+                                    dirs.numel(), _dev(path_off, torch.int64, "path_off"),
                                     _dev(path_lo, torch.int32, "path_lo"), _dev(path_hi, torch.int32, "path_hi"),
                                     path_lo.numel(), a[9], a[10], _dev(out_start, torch.int32, "out_start"),
                                     _stream(stream), None if opts is None else ctypes.byref(opts)))

@@ -151,12 +151,21 @@ def test_path_argument_errors_without_device(L):
     so = L.load()
     fake = ctypes.c_void_p(0x1000)
 
-    def path(max_query=100, path_off=fake, path_size=10, n_pairs=2, out_start=fake):
-        return so.rawalign_dtw_path(fake, 10, fake, fake, fake, 10, fake, fake, n_pairs, max_query, path_off,
-                                    fake, fake, path_size, fake, fake, out_start, None, None)
-    assert path(max_query=-1) == L.RAWALIGN_EINVAL and b"max_query" in so.rawalign_last_error()
+    def path(dir_off=fake, dirs=fake, dir_size=100, path_off=fake, path_size=10, n_pairs=2, out_start=fake):
+        return so.rawalign_dtw_path(fake, 10, fake, fake, fake, 10, fake, fake, n_pairs, dir_off, dirs, dir_size,
+                                    path_off, fake, fake, path_size, fake, fake, out_start, None, None)
+    assert path(dir_size=-1) == L.RAWALIGN_EINVAL and b"dir_size" in so.rawalign_last_error()
     assert path(path_size=-1) == L.RAWALIGN_EINVAL and b"path_size" in so.rawalign_last_error()
     assert path(path_off=None) == L.RAWALIGN_EINVAL and b"path_off" in so.rawalign_last_error()
+    assert path(dir_off=None) == L.RAWALIGN_EINVAL and b"dir_off" in so.rawalign_last_error()
+    assert path(dirs=None) == L.RAWALIGN_EINVAL and b"dirs" in so.rawalign_last_error()
     assert path(out_start=None) == L.RAWALIGN_EINVAL and b"out_start" in so.rawalign_last_error()
     assert path(n_pairs=-1) == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
-    assert path(n_pairs=0, path_off=None) == L.RAWALIGN_OK
+    assert path(n_pairs=0, path_off=None, dir_off=None) == L.RAWALIGN_OK
+
+
+def test_path_workspace_sizes(L):
+    """n * (64 * ceil(m / 2048) + 1) words per pair, packed in order."""
+    import numpy as np
+    off, words = L.path_workspace(np.array([3, 0, 5]), np.array([2048, 10, 2049]))
+    assert list(off) == [0, 3 * 65, 3 * 65] and words == 3 * 65 + 5 * 129

@@ -1,7 +1,7 @@
 """GPU parity of the warping path (rawalign_dtw_path, Sec. 2.4: the
 alignment path as an optional output) through the C ABI: score, end, start
 and every read event's level range bit for bit against the float oracle over
-interval widths in every columns-per-lane class, exact against the double
+interval widths in every columns-per-lane class and over several stripes, exact against the double
 oracle on dyadic inputs (where ties are frequent, so the tie order is
 exercised), the sentinels, and pairs of the single read and the uneven
 batch."""
@@ -23,11 +23,14 @@ def L():
     return lib
 
 
-def _gpu_path(L, b, max_query, path_off=None, path_size=None):
+def _gpu_path(L, b, path_off=None, path_size=None, dir_off=None, dir_words=None):
     import torch
     print(f"  gpu: path {b.name} pairs={b.n_pairs} max_n={int(b.q_len.max()) if b.n_pairs else 0} "
-          f"max_m={int(b.r_len.max()) if b.n_pairs else 0} max_query={max_query}", flush=True)
+          f"max_m={int(b.r_len.max()) if b.n_pairs else 0}", flush=True)
     db = L.DeviceBatch(b)
+    if dir_off is None:
+        dir_off, dir_words = L.path_workspace(b.q_len, b.r_len)
+    dirs = torch.empty(max(dir_words, 1), dtype=torch.int64, device="cuda")
     n = b.n_pairs
     rows = np.maximum(b.q_len.astype(np.int64), 0)
     if path_off is None:
@@ -37,8 +40,8 @@ def _gpu_path(L, b, max_query, path_off=None, path_size=None):
     lo = torch.full((path_size,), -7, dtype=torch.int32, device="cuda")
     hi = torch.full((path_size,), -7, dtype=torch.int32, device="cuda")
     start = torch.empty(n, dtype=torch.int32, device="cuda")
-    L.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, max_query,
-                        torch.from_numpy(path_off).cuda(), lo, hi, db.score, db.end, start)
+    L.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, torch.from_numpy(dir_off).cuda(),
+                        dirs[:dir_words], torch.from_numpy(path_off).cuda(), lo, hi, db.score, db.end, start)
     torch.cuda.synchronize()
     return (db.score.cpu().numpy(), db.end.cpu().numpy(), start.cpu().numpy(), lo.cpu().numpy(),
             hi.cpu().numpy(), path_off)
@@ -84,19 +87,22 @@ def _embedded(rng, spans, name, noise=0.1, dwell_p=0.35, value_fn=None):
 
 
 def test_path_interval_widths(L):
-    """Intervals from 1 to 2048 levels (every columns-per-lane class, lane
-    and class boundaries), plus unrelated random pairs."""
+    """Intervals from 1 to about 6,000 levels: every columns-per-lane class,
+    lane and class boundaries, and up to three stripes; plus unrelated
+    random pairs."""
     rng = np.random.default_rng(900)
     spans = [1, 2, 3, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257, 400, 511, 512, 513, 700, 1000, 1300,
-             1600, 1900, 2000]
-    b = _embedded(rng, spans, "path_widths")
-    res = _gpu_path(L, b, max_query=int(b.q_len.max()))
+             1600, 1900, 2000, 2047, 2048, 2049, 2500, 4000, 4097, 6000]
+    # mean dwell 2: the 6,000-level pair stays under the 16,384-event limit
+    # of regions over 4,096 levels
+    b = _embedded(rng, spans, "path_widths", dwell_p=0.5)
+    assert int(b.q_len.max()) <= 16384
+    res = _gpu_path(L, b)
     s, e, st, lo, hi, off = res
-    ok = np.flatnonzero(e - st + 1 <= 2048)
-    assert len(ok) >= len(spans) - 2
-    _check(b, res, ok)
+    assert (e - st + 1 > 4096).sum() >= 1 and (e - st + 1 > 2048).sum() >= 3
+    _check(b, res, range(b.n_pairs))
     b2 = W.random_pairs(rng, 60, (1, 500), (1, 900))
-    _check(b2, _gpu_path(L, b2, max_query=500), range(b2.n_pairs))
+    _check(b2, _gpu_path(L, b2), range(b2.n_pairs))
 
 
 def test_path_exact_on_dyadic_inputs(L):
@@ -104,18 +110,19 @@ def test_path_exact_on_dyadic_inputs(L):
     the paths equal the double oracle's, ties and all."""
     rng = np.random.default_rng(901)
     fn = lambda g, k: W.dyadic_values(g, k, -2.0, 2.0, 0.25)
-    b = _embedded(rng, [5, 40, 64, 130, 300, 600, 1024], "path_dyadic", value_fn=fn)
-    _check(b, _gpu_path(L, b, max_query=int(b.q_len.max())), range(b.n_pairs), exact64=True)
+    b = _embedded(rng, [5, 40, 64, 130, 300, 600, 1024, 2300], "path_dyadic", value_fn=fn)
+    _check(b, _gpu_path(L, b), range(b.n_pairs), exact64=True)
     b2 = W.random_pairs(rng, 80, (1, 120), (1, 160), value_fn=fn)
-    _check(b2, _gpu_path(L, b2, max_query=120), range(b2.n_pairs), exact64=True)
+    _check(b2, _gpu_path(L, b2), range(b2.n_pairs), exact64=True)
 
 
 def test_path_sentinels(L):
-    """-4: more events than max_query, or an interval wider than 2048
-    levels; -1: empty region; -2: invalid slice; an empty query has no
-    entries; a pair whose entries leave the path arrays is not written."""
+    """-4: a workspace range too small for the pair's interval (or a
+    negative offset); -1: empty region; -2: invalid slice; an empty query
+    has no entries; a pair whose entries leave the path arrays is not
+    written."""
     rng = np.random.default_rng(902)
-    b = _embedded(rng, [2600, 50, 50, 50, 50, 50], "path_sentinels")
+    b = _embedded(rng, [300, 50, 50, 50, 50, 50, 50], "path_sentinels")
     r_len = b.r_len.copy()
     q_len = b.q_len.copy()
     q_off = b.q_off.copy()
@@ -124,32 +131,33 @@ def test_path_sentinels(L):
     q_len[4] = 0
     b = W.Batch(b.name, b.q, b.r, q_off, q_len, b.r_off, r_len, b.cand_off, b.cand_cnt, b.n_events,
                 b.true_pair, b.meta)
-    max_query = int(b.q_len[1]) - 1          # pair 1 exceeds it
+    dir_off, words = L.path_workspace(b.q_len, b.r_len)
+    dir_off[0] = words - 10                     # pair 0's range runs past the workspace
+    dir_off[6] = -1
     rows = np.maximum(b.q_len.astype(np.int64), 0)
     off = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
     size = int(rows.sum())
+    own5 = slice(off[5], off[5] + rows[5])      # nobody else writes there
     off[5] = size - 3                           # pair 5 would run past the end
-    s, e, st, lo, hi, off = _gpu_path(L, b, max_query, off, size)
+    s, e, st, lo, hi, off = _gpu_path(L, b, off, size, dir_off, words)
     span = lambda p: slice(off[p], off[p] + int(b.q_len[p]))
-    assert (lo[span(0)] == -4).all() and (hi[span(0)] == -4).all() and e[0] - st[0] + 1 > 2048
-    assert (lo[span(1)] == -4).all() and (hi[span(1)] == -4).all()
+    assert (lo[span(0)] == -4).all() and (hi[span(0)] == -4).all()
+    assert (lo[span(6)] == -4).all() and (hi[span(6)] == -4).all()
     assert e[2] == -1 and (lo[span(2)] == -1).all() and (hi[span(2)] == -1).all()
     assert e[3] == -2 and (lo[span(3)] == -2).all() and (hi[span(3)] == -2).all()
     assert e[4] == -1 and st[4] == -1
-    assert (lo[size - 3:] == -7).all() and (hi[size - 3:] == -7).all()
+    assert (lo[own5] == -7).all() and (hi[own5] == -7).all()
+    _check(b, (s, e, st, lo, hi, off), [1])
 
 
 def test_path_single_read_and_uneven_batch_sample(L):
     """The single read's 10 candidates, and 40 pairs of the 100,000-pair
-    uneven batch (intervals up to 2048 levels), bit for bit."""
+    uneven batch, bit for bit."""
     b = W.single_read()
-    _check(b, _gpu_path(L, b, max_query=int(b.q_len.max())), range(b.n_pairs))
+    _check(b, _gpu_path(L, b), range(b.n_pairs))
     u = W.uneven_batch()
     rng = np.random.default_rng(903)
     pick = np.sort(rng.choice(u.n_pairs, size=40, replace=False))
     sub = u.subset(pick)
-    res = _gpu_path(L, sub, max_query=8000)
-    s, e, st, lo, hi, off = res
-    ok = np.flatnonzero((e >= 0) & (e - st + 1 <= 2048))
-    assert len(ok) >= 30
-    _check(sub, res, ok)
+    res = _gpu_path(L, sub)
+    _check(sub, res, range(sub.n_pairs))
