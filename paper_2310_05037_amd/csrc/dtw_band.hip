@@ -22,6 +22,10 @@
 //     cell reads is position W of the previous row (north of position W-1
 //     when the frame moves), so that cell is forced to +inf every row.
 // Per cell: the two shift selects, v_sub_f32, v_min3_f32 and v_add_f32.
+// The device planner (dtw_plan.hip, band mode) writes the sentinels and
+// lists the other pairs in two classes by frame width, longest first; each
+// class kernel takes its list from a persistent queue, and the two run
+// concurrently.
 #include "dtw_device.h"
 
 namespace ra {
