@@ -291,15 +291,18 @@ int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, cons
  * reachable.  band[p] >= m-1 gives plain subsequence DTW.
  *   Arguments as in rawalign_dtw_batch, plus band (device, int32 per pair).
  *   One wave per pair in a band-relative frame (frame positions follow the
- *   diagonal).  The pairs are planned on the device into two classes by
- *   frame width (up to 512 columns, and wider), each taken longest first
- *   from a persistent queue; the two class kernels run concurrently on
+ *   diagonal) when m <= n (at least as many events as levels, as in a
+ *   chained segment: about 3.3 events per level) and 2*min(band, m-1)+1 <=
+ *   2048; other pairs of at most 2048 levels use a frame over the whole
+ *   region with the cells outside the band forced to +inf.  The pairs are
+ *   planned on the device into three classes (band frames up to 512
+ *   columns, wider band frames, whole-region frames), each taken longest
+ *   first from a persistent queue; the class kernels run concurrently on
  *   internal streams joined back to `stream`.  Scratch: that of
  *   rawalign_dtw_batch, per (device, stream).
- *   Supported shapes: m <= n (at least as many events as levels, as in a
- *   chained segment: about 3.3 events per level) and 2*min(band, m-1)+1 <=
- *   2048; other pairs get the sentinel NaN, end -4.  A negative band or an
- *   invalid slice gives NaN, -2; n == 0 gives (0, -1), m == 0 (+inf, -1).
+ *   Pairs of more than 2048 levels with m > n or a band wider than 2048
+ *   columns get the sentinel NaN, end -4.  A negative band or an invalid
+ *   slice gives NaN, -2; n == 0 gives (0, -1), m == 0 (+inf, -1).
  */
 int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,

@@ -273,6 +273,109 @@ void k_band(PairArrays a, const int32_t *__restrict__ band, const int32_t *__res
     }
 }
 
+// Class 2: pairs the band-relative frame does not take (more levels than
+// events, so the band moves more than one column per row, or a band wider
+// than 2048 columns) in regions of at most 2048 levels.  The frame is the
+// whole region, as in the full-table kernels (lane k owns columns [kC,
+// kC+C)), and every cell outside its row's band is forced to +inf: a
+// subtraction, a compare and a select more per cell.  Each lane follows
+// c(i) of its own row with a counter.
+template <int C>
+RA_DEV void band_abs_pair(const BandView &bv, float &best, int &bj) {
+    const int lane = opaque_lane();
+    const int n = bv.n, m = bv.m, w = bv.w;
+    const __amdgpu_buffer_rsrc_t rrs = make_rsrc(bv.r, m);
+    const __amdgpu_buffer_rsrc_t qrs = make_rsrc(bv.q, n);
+    const int col0 = lane * C;
+    float rv[C], A[C];
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        const int j = col0 + v;
+        const float lv = bload(rrs, j < m ? j : m - 1);
+        rv[v] = j < m ? lv : kInf;
+        A[v] = 0.0f;   // row -1: the free start
+    }
+    // c = floor(i*m/n) of this lane's row i, rem = i*m mod n.
+    const int qd = m / n, rd = m % n;
+    int c = 0, rem = 0;
+    // Column -1 is +inf; so is the corner D(-1,-1) here, which gives row 0
+    // the same minimum as its north value D(-1,0) = 0.
+    float ecur = kInf, eprev, qv = 0.0f;
+    const int nm1 = n - 1;
+    float qa = uload(qrs, 0, nm1), qb = uload(qrs, 1, nm1);
+    const int T = n + 63;
+    for (int t = 0; t < T; ++t) {
+        const float q0 = qa;
+        qa = qb;
+        qb = uload(qrs, t + 2, nm1);
+        qv = dpp_shr1(q0, qv);
+        eprev = ecur;
+        ecur = dpp_shr1(kInf, A[C - 1]);
+        const int i = t - lane;
+        const bool valid = (unsigned)i < (unsigned)n;
+        const int a = c - w - col0;   // band of row i in lane positions: [a, a + 2w]
+        float diag = eprev, left = ecur;
+#pragma unroll
+        for (int v = 0; v < C; ++v) {
+            const float up = A[v];
+            float nv = fabsf(qv - rv[v]) + fminf(fminf(diag, up), left);
+            nv = (unsigned)(v - a) <= (unsigned)(2 * w) ? nv : kInf;
+            diag = up;
+            left = nv;
+            A[v] = valid ? nv : A[v];
+        }
+        if (valid) {
+            rem += rd;
+            const int carry = rem >= n ? 1 : 0;
+            rem -= carry ? n : 0;
+            c += qd + carry;
+        }
+    }
+    best = kInf;
+    bj = 0x7fffffff;
+#pragma unroll
+    for (int v = 0; v < C; ++v)
+        if (col0 + v < m) take_min(best, bj, A[v], col0 + v);
+    wave_min(best, bj);
+    if (!(best < kInf)) bj = -1;
+}
+
+template <int H>
+RA_DEV void band_abs_dispatch(int h, const BandView &bv, float &best, int &bj) {
+    if constexpr (H <= kBandMaxFrame / 128) {
+        if (h == H)
+            band_abs_pair<2 * H>(bv, best, bj);
+        else
+            band_abs_dispatch<H + 1>(h, bv, best, bj);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_band_abs(PairArrays a, const int32_t *__restrict__ band, const int32_t *__restrict__ list,
+                const int32_t *__restrict__ count, int32_t *queue) {
+    const int n_items = *count;
+    int it = 0;
+    if (__lane_id() == 0) it = atomicAdd(queue, 1);
+    int item = __builtin_amdgcn_readfirstlane(it);
+    while (item < n_items) {
+        const int p = list[item];
+        const int n = a.q_len[p];
+        const int m = a.r_len[p];
+        const int wraw = band[p];
+        const int w = wraw < m - 1 ? wraw : m - 1;
+        const BandView bv{a.q + a.q_off[p], a.r + a.r_off[p], n, m, w, 2 * w + 1};
+        float best = __builtin_nanf("");
+        int bj = -2;
+        band_abs_dispatch<1>((m + 127) / 128, bv, best, bj);
+        if (__lane_id() == 0) {
+            a.out_score[p] = best;
+            a.out_end[p] = bj;
+        }
+        if (__lane_id() == 0) it = atomicAdd(queue, 1);
+        item = __builtin_amdgcn_readfirstlane(it);
+    }
+}
+
 // Class 0 (C <= 8) fits 64 VGPRs: eight waves per SIMD; class 1 four.
 #define RA_BAND_LO k_band<1, kBandLoMaxH, 8>
 #define RA_BAND_HI k_band<kBandLoMaxH + 1, kBandMaxFrame / 128, 4>
@@ -284,8 +387,10 @@ hipError_t launch_band(int cls, const PairArrays &a, const int32_t *band, int gr
     int32_t *queue = s.queue + cls;
     if (cls == 0)
         hipLaunchKernelGGL(RA_BAND_LO, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
-    else
+    else if (cls == 1)
         hipLaunchKernelGGL(RA_BAND_HI, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
+    else
+        hipLaunchKernelGGL(k_band_abs, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
     return hipGetLastError();
 }
 
@@ -293,8 +398,10 @@ int band_blocks_per_cu(int cls) {
     int nb = 0;
     if (cls == 0)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_LO, 64, 0);
-    else
+    else if (cls == 1)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_HI, 64, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_band_abs, 64, 0);
     return nb > 0 ? nb : 1;
 }
 

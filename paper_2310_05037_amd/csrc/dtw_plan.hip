@@ -14,11 +14,12 @@ struct PlanArgs {
 };
 
 // Banded pairs (dtw_band.hip): class 0 for frames of at most kBandLoMaxH*128
-// columns, class 1 for wider ones, longest first by the frame cells swept.
-// Pairs that need no kernel get their result here: NaN/-2 for an invalid
-// slice or a negative band, (0, -1) for an empty query, (+inf, -1) for an
-// empty region, NaN/-4 for a shape the banded kernel does not take (more
-// levels than events, or a band wider than one wave's frame).
+// columns, class 1 for wider ones, longest first by the frame cells swept;
+// class 2 for the shapes the band-relative frame does not take (more levels
+// than events, or a band wider than one wave's frame) when the whole region
+// fits one wave's frame.  Pairs that need no kernel get their result here:
+// NaN/-2 for an invalid slice or a negative band, (0, -1) for an empty
+// query, (+inf, -1) for an empty region, NaN/-4 for the remaining shapes.
 RA_DEV int band_classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
     const PairArrays &a = pa.a;
     const int n = a.q_len[p];
@@ -37,6 +38,13 @@ RA_DEV int band_classify(const PlanArgs &pa, int64_t p, int &bucket, float &scor
     const int w = wraw < m - 1 ? wraw : m - 1;
     const int W = 2 * w + 1;
     if (m > n || W > kBandMaxFrame) {
+        if (m <= kBandMaxFrame) {
+            const float work = (float)(n + 64) * (float)(128 * ((m + 127) / 128)) + 1.0f;
+            int b = (int)(4.0f * __log2f(work));
+            b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
+            bucket = kBuckets - 1 - b;
+            return 2;
+        }
         score = __builtin_nanf("");
         end = -4;
         return -1;

@@ -177,9 +177,11 @@ hipError_t launch_span_prep(const int32_t *end, int64_t n_pairs, int32_t *rev_le
 hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_t n_pairs, int32_t *out_start,
                               hipStream_t stream);
 // Banded subsequence DTW, one wave per pair.  The planner (same scratch and
-// kernels as the striped routes) gives every pair a band class and writes
-// the sentinels of the pairs that need no kernel; each class kernel then
-// takes its list longest first from its persistent queue.
+// kernels as the striped routes) gives every pair a band class (two frame
+// widths of the band-relative kernel, and the whole-region kernel for the
+// shapes it does not take) and writes the sentinels of the pairs that need
+// no kernel; each class kernel then takes its list longest first from its
+// persistent queue.
 constexpr int kBandMaxFrame = 64 * 32;   // band columns one wave takes (C <= 32 per lane)
 constexpr int kBandLoMaxH = 4;           // class 0: frames of at most 4*128 columns (C <= 8)
 hipError_t launch_band_plan(const PairArrays &a, const int32_t *band, int64_t n_pairs, const PlanScratch &s,

@@ -785,10 +785,10 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
     const ra::PlanScratch ps = plan_view(*s);
     hipError_t e = ra::launch_band_plan(a, band, n_pairs, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "banded planning");
-    // The two band classes run concurrently on internal streams joined back
-    // to the caller's stream.
+    // The band classes run concurrently on internal streams joined back to
+    // the caller's stream.
     if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    for (int cls = 0; cls < 2; ++cls) {
+    for (int cls = 0; cls < 3; ++cls) {
         if ((e = hipStreamWaitEvent(s->sub[cls], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         const int grid = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(cls), n_pairs);
         e = ra::launch_band(cls, a, band, grid, ps, s->sub[cls]);

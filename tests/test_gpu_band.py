@@ -108,9 +108,10 @@ def test_band_exact_on_dyadic_inputs(L):
 
 
 def test_band_sentinels(L):
-    """m > n and frames wider than 2048 columns: NaN, -4; a negative band
-    or an invalid slice: NaN, -2; empty query (0, -1); empty region
-    (+inf, -1)."""
+    """More than 2048 levels with a band frame wider than 2048 columns (or
+    m > n): NaN, -4; a negative band or an invalid slice: NaN, -2; empty
+    query (0, -1); empty region (+inf, -1).  m > n in a short region goes
+    to the whole-region kernel and matches the oracle."""
     rng = np.random.default_rng(11)
     ns = [50, 3000, 20, 0, 10, 40, 40]
     ms = [80, 2500, 10, 5, 0, 30, 30]
@@ -121,10 +122,33 @@ def test_band_sentinels(L):
     b = W.Batch(b.name, b.q, b.r, q_off, b.q_len, b.r_off, b.r_len, b.cand_off, b.cand_cnt, b.n_events,
                 b.true_pair, b.meta)
     s, e = _gpu_band(L, b, band)
-    assert math.isnan(s[0]) and e[0] == -4 and math.isnan(s[1]) and e[1] == -4
+    assert e[0] >= 0 and math.isnan(s[1]) and e[1] == -4
     assert math.isnan(s[2]) and e[2] == -2 and math.isnan(s[6]) and e[6] == -2
     assert s[3] == 0.0 and e[3] == -1 and s[4] == np.inf and e[4] == -1
-    _check(b, band, s, e, np.array([5]))
+    _check(b, band, s, e, np.array([0, 5]))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_band_more_levels_than_events_and_wide_bands(L, seed):
+    """The whole-region kernel: regions up to 2048 levels with up to 4
+    levels per event (the band moves several columns per row), and bands
+    wider than 2048 columns; half-widths from 0 to past the table; every
+    columns-per-lane class."""
+    rng = np.random.default_rng(700 + seed)
+    ns, ms, ws = [], [], []
+    for m in [1, 2, 5, 63, 64, 65, 128, 129, 300, 700, 1024, 1500, 2000, 2048]:
+        for ratio in (1.3, 2.0, 4.0):
+            n = max(1, int(m / ratio))
+            for w in (0, 1, int(rng.integers(0, m + 1)), m + 3):
+                ns.append(n), ms.append(m), ws.append(w)
+    for m in (1100, 1600, 2048):                  # m <= n with a frame wider than 2048
+        ns.append(m + 50), ms.append(m), ws.append(m - 1)
+    b = _pairs(rng, ns, ms, f"band_abs_{seed}")
+    band = np.array(ws, np.int32)
+    s, e = _gpu_band(L, b, band)
+    # narrow bands that move several columns per row leave no path: (+inf, -1)
+    assert (e >= -1).all() and (e >= 0).sum() > len(ns) // 2
+    _check(b, band, s, e)
 
 
 def test_band_chained_segments(L):
@@ -140,8 +164,8 @@ def test_band_chained_segments_full_size_sampled(L):
     """The 100,000 chained segments of the banded benchmark in one call (the
     launch the benchmark times): on a sample stratified by frame width (every
     columns-per-lane class) plus random pairs, scores and ends bit for bit
-    against the float oracle; every pair with more levels than events carries
-    the -4 sentinel and no other does."""
+    against the float oracle; the pairs with more levels than events are
+    checked too, and only unsupported shapes carry the -4 sentinel."""
     ab = W.anchored_chains()
     b, band = W.chained_segments(ab)
     s, e = _gpu_band(L, b, band)
@@ -155,7 +179,11 @@ def test_band_chained_segments_full_size_sampled(L):
     pick.append(rng.choice(b.n_pairs, size=120, replace=False))
     pairs = np.unique(np.concatenate(pick))
     _check(b, band, s, e, pairs)
-    assert np.array_equal(np.flatnonzero(e == -4), np.flatnonzero(m > n))
+    unsupported = (m > 2048) & ((m > n) | (2 * w + 1 > 2048))
+    assert np.array_equal(np.flatnonzero(e == -4), np.flatnonzero(unsupported))
     ok = e >= 0
-    assert ok.sum() == b.n_pairs - int((m > n).sum())
+    assert ok.sum() == b.n_pairs - int(unsupported.sum())
+    more = np.flatnonzero((m > n) & ~unsupported)
+    if len(more):
+        _check(b, band, s, e, more)
     assert np.all(np.isfinite(s[ok]))
