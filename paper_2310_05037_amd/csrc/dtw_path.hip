@@ -163,20 +163,35 @@ __global__ void k_path_trace(PathArgs pa) {
     const uint64_t *base = pa.dirs + pa.dir_off[p];
     int i = n - 1, j = L - 1;
     hi[i] = s + j;
+    // Column j as (stripe sj, lane li, bit pair v), stepped down with j.
+    int sj = j / Wst, li = (j - sj * Wst) / C, v = (j - sj * Wst) - li * C;
+    // The word of the current cell is kept while west moves stay inside it.
+    int64_t widx = -1;
+    uint64_t w = 0;
     // Every step lowers i + j; the edges of the table allow only one move
     // (west along row 0, north along column 0), whatever the codes say.
     for (;;) {
         lo[i] = s + j;
         if (i == 0 && j == 0) break;
-        const int sj = j / Wst, jl = j - sj * Wst;
-        const uint64_t w = base[((int64_t)sj * n + i) * kPathWordsPerRow + jl / C];
-        int d = (int)((w >> (2 * (jl % C))) & 3);
+        const int64_t k = ((int64_t)sj * n + i) * kPathWordsPerRow + li;
+        if (k != widx) {
+            widx = k;
+            w = base[k];
+        }
+        int d = (int)((w >> (2 * v)) & 3);
         if (i == 0) d = kPathW;
         else if (j == 0) d = kPathN;
-        if (d == kPathW) {
+        if (d != kPathN) {   // west or north-west: one column left
             --j;
-        } else {
-            if (d == kPathNW) --j;
+            if (--v < 0) {
+                v = C - 1;
+                if (--li < 0) {
+                    li = 63;
+                    --sj;
+                }
+            }
+        }
+        if (d != kPathW) {   // north or north-west: one row up
             --i;
             hi[i] = s + j;
         }
