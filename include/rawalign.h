@@ -264,8 +264,8 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
  *              (2 bits per cell and a stripe edge).  The interval is at most
  *              m levels, so n * (64 * ceil(m / 2048) + 1) words always
  *              suffice.  A pair whose range does not hold its interval gets
- *              -4 in every entry; pairs may share words only if they are not
- *              both aligned in one call.
+ *              -4 in every entry.  The ranges of the pairs of one call must
+ *              not overlap.
  *   Pairs without an alignment get their end sentinel in every entry (-1
  *   empty region, -2 invalid slice); an empty query has no entries.
  *   Entries of a pair whose range leaves [0, path_size) are not written.
