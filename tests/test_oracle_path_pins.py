@@ -88,3 +88,19 @@ def test_path_special_cases(oracle_mod):
     for qq, rr in ((np.zeros(0, np.float32), r), (q, np.zeros(0, np.float32))):
         _, e, s, _, lo, hi = oracle_mod.dtw_path_f64(qq, rr)
         assert e == -1 and s == -1 and (lo == -1).all() and (hi == -1).all()
+
+
+def test_path_float_equals_double_on_exact_inputs(oracle_mod):
+    """Quarter-step inputs keep every sum exact in float: the float path
+    (start from the float reverse pass, directions from the float table) is
+    the double one, ties and all."""
+    rng = np.random.default_rng(75)
+    for _ in range(80):
+        n = int(rng.integers(1, 50))
+        m = int(rng.integers(1, 70))
+        q = (rng.integers(-8, 9, n) * 0.25).astype(np.float32)
+        r = (rng.integers(-8, 9, m) * 0.25).astype(np.float32)
+        c, e, s, g, lo, hi = oracle_mod.dtw_path_f64(q, r)
+        c32, e32, s32, g32, lo32, hi32 = oracle_mod.dtw_path_f32(q, r)
+        assert float(c32) == c and (e32, s32) == (e, s) and float(g32) == g
+        assert list(lo32) == list(lo) and list(hi32) == list(hi)
