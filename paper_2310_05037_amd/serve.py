@@ -92,6 +92,8 @@ class ReadState:
     done: bool = False
     status: str = "waiting"      # waiting | active | mapped | unmapped | cancelled | failed
     results: list = field(default_factory=list)   # per chunk: (best_pair, score, mapped, c_dtw[], end[])
+    inflight: bool = False       # a launched tick holds this read's chunk (its kernels may write its rows)
+    release_pending: bool = False   # finished while in flight: free the rows when that tick returns
 
     def chunk_ready_time(self, c: int, period: float) -> float:
         return self.arrival + c * period
@@ -176,16 +178,33 @@ class Engine:
         return st
 
     def cancel(self, rid: int):
+        """Stop a read.  If a tick holding its chunk is still running, its
+        rows stay allocated until that tick returns, since the running
+        kernels still write them."""
         st = self.by_id.get(rid)
         if st is not None and not st.done:
             self._finish(st, "cancelled")
 
     # ---- scheduling ------------------------------------------------------------
-    def _finish(self, st: ReadState, status: str):
+    def _release(self, st: ReadState):
         if st.admitted and st.row_off is not None:
             # one block per read: the candidates' rows are contiguous
             self.arena.release(int(st.row_off[0]), int(st.r_len.astype(np.int64).sum()))
         st.row_off = None
+        st.release_pending = False
+
+    def _returned(self, b: "TickBatch"):
+        """The tick of batch b is over: its reads' rows are no longer written."""
+        for st in b.reads:
+            st.inflight = False
+            if st.release_pending:
+                self._release(st)
+
+    def _finish(self, st: ReadState, status: str):
+        if st.inflight:
+            st.release_pending = True   # freed by _returned when its tick is back
+        else:
+            self._release(st)
         st.done = True
         st.status = status
         self.n_done += 1
@@ -249,12 +268,14 @@ class Engine:
     def _fail(self, b: TickBatch):
         """A backend error fails only the reads of that tick."""
         self.failed_ticks += 1
+        self._returned(b)
         for st in b.reads:
             if not st.done:
                 self._finish(st, "failed")
 
     def _complete(self, b: TickBatch, results, t_done: float) -> int:
         score, end, best, best_score, mapped = results
+        self._returned(b)
         self.ticks += 1
         self.jobs += b.n_jobs
         self.cells += b.cells
@@ -301,6 +322,8 @@ class Engine:
         if not ready:
             return done
         b = self._batch(ready)
+        for st in b.reads:
+            st.inflight = True
         if self.async_backend:
             try:
                 token = self.backend.launch(b, self.b_match, self.threshold)

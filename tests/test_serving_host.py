@@ -28,6 +28,8 @@ def drive(eng, clock, dt=None, max_ticks=100000):
                 if dt:
                     clock.t += dt
                 continue
+            if eng.all_done():        # the last tick failed: nothing left to run
+                continue
             nxt = eng.next_event_time()
             if nxt is None:
                 raise RuntimeError("stuck")
@@ -230,3 +232,80 @@ def test_ticks_in_flight_give_the_same_results():
         assert a.status == b.status and len(a.results) == len(b.results)
         for x, y in zip(a.results, b.results):
             assert x[:3] == y[:3] and np.array_equal(x[3], y[3]) and np.array_equal(x[4], y[4])
+
+
+class OverlapCheckingAsync(AsyncOracle):
+    """Async oracle backend that asserts, at every launch, that the new
+    tick's rows are disjoint from the rows of every tick still in flight
+    (on a GPU those kernels would still be writing them)."""
+    slots = 3
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.live = {}
+
+    def launch(self, b, b_match, threshold):
+        iv = [(int(o), int(o) + int(n)) for o, n in zip(b.row_off, b.r_len)]
+        for other in self.live.values():
+            for a0, a1 in iv:
+                for b0, b1 in other:
+                    assert a1 <= b0 or b1 <= a0, "rows of a new tick overlap a tick in flight"
+        tok = super().launch(b, b_match, threshold)
+        self.live[tok] = iv
+        return tok
+
+    def poll(self, tok):
+        res = super().poll(tok)
+        if res is not None:
+            del self.live[tok]
+        return res
+
+
+def test_cancel_in_flight_keeps_rows_until_the_tick_returns():
+    """A read cancelled while its tick runs keeps its rows until that tick
+    returns: a waiting read that would fit in the freed block is admitted
+    only afterwards, so no two ticks in flight ever share rows."""
+    wl = small_workload(n_reads=3)
+    need = sum(int(rd.r_len.sum()) for rd in wl.reads)
+    clock = VClock()
+    be = OverlapCheckingAsync(wl.r, need, delay=5)
+    eng = serve.Engine(be, need, wl.chunk, wl.period, clock=clock)
+    for i, rd in enumerate(wl.reads):
+        eng.submit(i, 0.0, rd.events, rd.r_off, rd.r_len)
+    r0 = wl.reads[0]
+    eng.submit(3, 0.0, r0.events, r0.r_off, r0.r_len)   # fits exactly in read 0's block
+    eng.tick()
+    assert all(st.inflight for st in eng.reads[:3]) and eng.arena.used == need
+    eng.cancel(0)
+    assert eng.reads[0].status == "cancelled" and eng.reads[0].release_pending
+    assert eng.arena.used == need                        # still written by the running tick
+    eng.tick()
+    assert not eng.reads[3].admitted
+    drive(eng, clock)
+    assert eng.reads[0].status == "cancelled" and eng.reads[3].admitted
+    assert eng.reads[3].status in ("mapped", "unmapped")
+    assert eng.arena.used == 0 and not be.live
+
+
+def test_failed_tick_releases_cancelled_rows():
+    """A tick that fails returns its reads' rows too, cancelled ones included."""
+    wl = small_workload(n_reads=3)
+    clock = VClock()
+
+    class FailingAsync(OverlapCheckingAsync):
+        def poll(self, tok):
+            res = super().poll(tok)
+            if res is not None:
+                raise RuntimeError("injected failure")
+            return res
+
+    be = FailingAsync(wl.r, 1 << 20, delay=2)
+    eng = serve.Engine(be, 1 << 20, wl.chunk, wl.period, clock=clock)
+    for i, rd in enumerate(wl.reads):
+        eng.submit(i, 0.0, rd.events, rd.r_off, rd.r_len)
+    eng.tick()
+    eng.cancel(1)
+    assert eng.arena.used > 0
+    drive(eng, clock)
+    assert eng.arena.used == 0 and eng.failed_ticks >= 1
+    assert eng.reads[1].status == "cancelled"
