@@ -164,7 +164,10 @@ int rawalign_dtw_extend(const float *q, int64_t q_size, const int64_t *q_off, co
  * Score = b_match * N_Read - C_DTW (double precision, from the float C_DTW);
  * the highest score wins (smallest pair index on ties) and the read is mapped
  * iff that score >= threshold.  The paper's defaults are b_match = 0.4 and
- * threshold = 20 (Sec. 3.1.5).
+ * threshold = 20 (Sec. 3.1.5).  A candidate whose C_DTW is NaN (the sentinel
+ * of a pair that was not aligned) is skipped: it cannot win, and it does not
+ * hide the candidates after it; a read whose candidates are all NaN gets
+ * out_best -1, score -inf, not mapped.
  *   score                     device float32 per pair (C_DTW from a DTW call)
  *   cand_off                  device int64 per read;  cand_cnt, n_events device int32 per read
  *   out_best                  device int32 per read: winning pair index, -1 if no candidates
@@ -346,7 +349,8 @@ int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_o
  *   - read k owns chains cand_off[k] .. +cand_cnt[k]; chain c scores
  *     b_match * chain_events[c] - cost (double), where chain_events counts
  *     the read events the chain aligns; the highest score wins (smallest
- *     chain index on ties) and the read is mapped iff it is >= threshold.
+ *     chain index on ties) and the read is mapped iff it is >= threshold;
+ *     a chain whose cost is NaN is skipped, as in rawalign_decide.
  *   gap_cost (n_gaps floats, e.g. from rawalign_dtw_global_batch),
  *   chain_gap_off int64, chain_gap_cnt/chain_events int32 per chain,
  *   cand_off int64, cand_cnt int32 per read; outputs as in rawalign_decide

@@ -202,6 +202,8 @@ def decide(cost, cand_off, cand_cnt, n_events, b_match=B_MATCH, threshold=SCORE_
     and has n_events[k] aligned read events.  Score = b_match*N_Read - C_DTW
     in double precision.  The best candidate is the highest score, the
     smallest pair index on ties; the read is mapped iff that score >= threshold.
+    A NaN cost marks a pair that was not aligned (an invalid or unsupported
+    pair): it is not a candidate.
     Returns (best pair index or -1, best score or -inf, mapped flag).
     """
     n_reads = len(cand_off)
@@ -211,6 +213,8 @@ def decide(cost, cand_off, cand_cnt, n_events, b_match=B_MATCH, threshold=SCORE_
     for k in range(n_reads):
         N = float(n_events[k])
         for p in range(int(cand_off[k]), int(cand_off[k]) + int(cand_cnt[k])):
+            if np.isnan(cost[p]):
+                continue
             s = b_match * N - float(cost[p])
             if best[k] < 0 or s > best_score[k]:
                 best[k] = p
@@ -297,13 +301,16 @@ def decide_chains(chain_cost, chain_events, cand_off, cand_cnt, b_match=B_MATCH,
     read scores b_match * chain_events[c] - chain_cost[c] (double precision),
     where chain_events[c] counts the read events its chain aligns; the
     highest score wins, the smallest candidate index on ties, and the read is
-    mapped iff that score >= threshold."""
+    mapped iff that score >= threshold.  A chain whose cost is NaN (a gap
+    range outside the gap array, or an invalid gap) is not a candidate."""
     n_reads = len(cand_off)
     best = np.full(n_reads, -1, dtype=np.int32)
     best_score = np.full(n_reads, -np.inf, dtype=np.float64)
     mapped = np.zeros(n_reads, dtype=np.uint8)
     for k in range(n_reads):
         for c in range(int(cand_off[k]), int(cand_off[k]) + int(cand_cnt[k])):
+            if np.isnan(chain_cost[c]):
+                continue
             s = b_match * float(chain_events[c]) - float(chain_cost[c])
             if best[k] < 0 or s > best_score[k]:
                 best[k] = c

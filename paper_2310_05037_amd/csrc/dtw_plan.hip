@@ -293,12 +293,17 @@ __global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const
         return;
     }
     // Score = B_Match * N_Read - C_DTW; highest wins, smallest index on ties.
-    // Anchored chains count the events each chain aligns.
+    // Anchored chains count the events each chain aligns.  A NaN cost (the
+    // sentinel of a pair that was not aligned: invalid slice, unsupported
+    // shape) is no candidate at all, so it can neither win nor block a later
+    // candidate.
     const double bonus = per_candidate ? 0.0 : b_match * (double)n_events[k];
     int32_t best = -1;
     double bs = -__builtin_inf();
     for (int c = 0; c < cnt; ++c) {
-        const double s = (per_candidate ? b_match * (double)n_events[p0 + c] : bonus) - (double)score[p0 + c];
+        const float cost = score[p0 + c];
+        if (cost != cost) continue;
+        const double s = (per_candidate ? b_match * (double)n_events[p0 + c] : bonus) - (double)cost;
         if (best < 0 || s > bs) {
             best = (int32_t)(p0 + c);
             bs = s;

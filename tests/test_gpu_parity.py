@@ -246,6 +246,10 @@ def test_decide_matches_oracle(L):
     s32, _, _ = oracle.dtw_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
     s32 = s32.copy()
     s32[5] = np.inf  # a candidate with an empty region
+    # NaN sentinels (pairs that were not aligned) are no candidates: one
+    # before a read's other candidates, and a read with nothing else
+    s32[int(b.cand_off[1])] = np.nan
+    s32[int(b.cand_off[2]):int(b.cand_off[2] + b.cand_cnt[2])] = np.nan
     dev = "cuda"
     n_reads = len(b.cand_off)
     ob = torch.empty(n_reads, dtype=torch.int32, device=dev)
@@ -260,6 +264,7 @@ def test_decide_matches_oracle(L):
                           ob, os_, om, b_match=bm, threshold=th)
         torch.cuda.synchronize()
         rb, rs, rm = oracle.decide(s32, b.cand_off, cnt, b.n_events, bm, th)
+        assert rb[1] > b.cand_off[1] and rb[2] == -1 and rs[2] == -np.inf
         assert np.array_equal(ob.cpu().numpy(), rb)
         assert np.array_equal(os_.cpu().numpy(), rs)
         assert np.array_equal(om.cpu().numpy(), rm)

@@ -147,6 +147,15 @@ def test_decide_chains_worked_example(oracle_mod):
     assert mapped.tolist() == [1, 0, 0, 1, 0]
 
 
+def test_decide_chains_skips_nan_costs(oracle_mod):
+    """A chain whose cost is NaN (its gap range left the gap array) is no
+    candidate: the next chain of the read still wins.  Hand-computed: read 0
+    has a NaN chain then 0.4*100 - 10 = 30; read 1 has only a NaN chain."""
+    cost = np.array([np.nan, 10.0, np.nan], np.float32)
+    best, score, mapped = oracle_mod.decide_chains(cost, [100, 100, 100], [0, 2], [2, 1])
+    assert best.tolist() == [1, -1] and score.tolist() == [30.0, -np.inf] and mapped.tolist() == [1, 0]
+
+
 def test_anchored_workload_structure():
     """Every gap lies inside q and r and is empty on both sides or on
     neither; a chain's gaps advance through the read and the reference;

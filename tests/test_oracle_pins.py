@@ -334,3 +334,17 @@ def test_decision_worked_examples(oracle_mod):
     # equal scores: the smaller pair index wins
     b2, _, _ = oracle_mod.decide(np.array([5.0, 5.0], np.float32), [0], [2], [100])
     assert b2.tolist() == [0]
+
+
+def test_decision_skips_nan_sentinels(oracle_mod):
+    """A NaN cost is the sentinel of a pair that was not aligned: it is not a
+    candidate.  Hand-computed, N = 100 (bonus 40): read 0 has the sentinel
+    first and a mapping candidate (40 - 10 = 30) after it; read 1 has only
+    sentinels (no candidate: -1, -inf); read 2 has a sentinel between two
+    real candidates (scores 15 and 25)."""
+    nan = np.float32(np.nan)
+    cost = np.array([nan, 10.0, nan, nan, 25.0, nan, 15.0], np.float32)
+    best, score, mapped = oracle_mod.decide(cost, [0, 2, 4], [2, 2, 3], [100, 100, 100])
+    assert best.tolist() == [1, -1, 6]
+    assert score.tolist() == [30.0, -np.inf, 25.0]
+    assert mapped.tolist() == [1, 0, 1]
