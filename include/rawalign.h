@@ -131,6 +131,35 @@ int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, 
                           const rawalign_opts *opts);
 
 /*
+ * Allocation-free batched subsequence DTW, for callers that cannot allocate
+ * device memory: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (bit for bit)
+ * and sentinels as rawalign_dtw_batch / rawalign_dtw_batch_ex with default
+ * options (persistent queues, striped kernels, every kernel on `stream`),
+ * but the planning lists and the multi-stripe kernel's edge slots live in
+ * one fixed device array of RAWALIGN_NOALLOC_SCRATCH_BYTES (33.5 MiB) per
+ * GPU, which the library holds from its first use on that GPU until the
+ * process ends.  The call makes no hipMalloc, hipFree or other allocating
+ * call; the address of the array on the current device is looked up once
+ * per device, on the first call there.
+ *   - n_pairs > RAWALIGN_NOALLOC_MAX_PAIRS returns RAWALIGN_EINVAL before
+ *     anything is enqueued.
+ *   - At most RAWALIGN_NOALLOC_EDGE_SLOTS waves sweep regions longer than
+ *     4096 levels at once (the other routes use their usual grids), so large
+ *     batches of long regions run slower than through rawalign_dtw_batch_ex.
+ *   - Every call on one GPU uses the same array, which keeps the last call's
+ *     contents (the planning kernels clear what must start at zero).  Calls
+ *     that overlap in time on one GPU (on different streams, or from several
+ *     threads) race on it and give wrong results: serialise them.
+ */
+#define RAWALIGN_NOALLOC_MAX_PAIRS 131072
+#define RAWALIGN_NOALLOC_EDGE_SLOTS 512
+#define RAWALIGN_NOALLOC_SCRATCH_BYTES 35129856
+int rawalign_dtw_batch_noalloc(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                               const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                               int64_t n_pairs, float *out_score, int32_t *out_end, void *stream);
+
+/*
  * Streaming extension for Read Until (Sec. 1, Sec. 3.1.2: reads arrive in
  * chunks and a decision is taken after each one).  Job k continues the
  * alignment of one (read, candidate) pair by the events of a new chunk:

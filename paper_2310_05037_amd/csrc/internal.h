@@ -193,6 +193,20 @@ hipError_t launch_chain_sum(const float *gap_cost, int64_t n_gaps, const int64_t
                             const int32_t *chain_gap_cnt, int64_t n_chains, float *out_chain_cost,
                             hipStream_t stream);
 
+// Allocation-free batch (rawalign_dtw_batch_noalloc): planning words, pair
+// lists for at most kNoallocMaxPairs pairs and kNoallocEdgeSlots stripe-edge
+// slots (so at most that many resident multi-stripe waves) in one fixed
+// device array per GPU (dtw_noalloc.hip).  noalloc_scratch looks up the
+// calling device's copy (once per device, with that device current) and
+// returns its views; it allocates nothing.
+constexpr int64_t kNoallocMaxPairs = 1 << 17;
+constexpr int kNoallocEdgeSlots = 512;
+constexpr size_t kNoallocScratchBytes =
+    ((sizeof(int32_t) * ((size_t)kNumRoutes * kBuckets + 2 * kNumRoutes) + 255) / 256 * 256) +
+    ((sizeof(int32_t) * (size_t)kNumRoutes * kNoallocMaxPairs + 255) / 256 * 256) +
+    sizeof(float) * (size_t)kNoallocEdgeSlots * kEdgeCap;
+hipError_t noalloc_scratch(int dev, PlanScratch &out);
+
 // Occupancy-derived resident workgroups per CU of each route's kernel.
 int single_lo_blocks_per_cu(bool extend);
 int single_hi_blocks_per_cu(bool extend);

@@ -294,11 +294,24 @@ int check_call(const Call &c) {
 
 int grid_of(int cus, int per_cu_opt, int occupancy) { return cus * (per_cu_opt ? per_cu_opt : occupancy); }
 
-int run(const Call &c, const rawalign_opts &o) {
+static_assert(RAWALIGN_NOALLOC_MAX_PAIRS == ra::kNoallocMaxPairs, "allocation-free pair limit");
+static_assert(RAWALIGN_NOALLOC_EDGE_SLOTS == ra::kNoallocEdgeSlots, "allocation-free edge slots");
+static_assert(RAWALIGN_NOALLOC_SCRATCH_BYTES == ra::kNoallocScratchBytes, "allocation-free scratch size");
+
+// noalloc: take the planning lists and edge slots from the fixed device
+// array (ra::noalloc_scratch) instead of the per-stream buffers; every
+// kernel runs on c.stream, with no timing events and no allocation.
+int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
     int rc = check_call(c);
     if (rc) return rc;
     rc = check_opts(o);
     if (rc) return rc;
+    if (noalloc && (o.streams != 1 || (o.flags & RAWALIGN_FLAG_TIMING) || o.long_kernel != RAWALIGN_LONG_STRIPED ||
+                    c.bound != ra::kBoundSubseq || c.rows))
+        return fail(RAWALIGN_EINVAL, "allocation-free call: one stream, no timing, striped kernels, plain batch");
+    if (noalloc && c.n_pairs > ra::kNoallocMaxPairs)
+        return fail(RAWALIGN_EINVAL, "allocation-free call: n_pairs " + std::to_string(c.n_pairs) + " exceeds " +
+                                         std::to_string(ra::kNoallocMaxPairs));
     if (c.rows && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
         return fail(RAWALIGN_EINVAL, "extend: opts.long_kernel must be RAWALIGN_LONG_STRIPED");
     if ((c.bound != ra::kBoundSubseq || c.reverse) && o.long_kernel == RAWALIGN_LONG_ANTIDIAG)
@@ -335,9 +348,17 @@ int run(const Call &c, const rawalign_opts &o) {
     const bool timing = (o.flags & RAWALIGN_FLAG_TIMING) != 0;
     const bool concurrent = o.streams == 3;
     StreamScratch *s = nullptr;
-    rc = get_scratch(dev, c.stream, c.n_pairs, cfg.multi_grid, antidiag ? cfg.antidiag_grid : 0, timing, concurrent,
-                     s);
-    if (rc) return rc;
+    ra::PlanScratch fixed;
+    if (noalloc) {
+        const hipError_t e = ra::noalloc_scratch(dev, fixed);
+        if (e != hipSuccess) return hip_fail(e, "allocation-free scratch (hipGetSymbolAddress)");
+        // One edge slot per resident multi-stripe wave.
+        cfg.multi_grid = std::min(cfg.multi_grid, ra::kNoallocEdgeSlots);
+    } else {
+        rc = get_scratch(dev, c.stream, c.n_pairs, cfg.multi_grid, antidiag ? cfg.antidiag_grid : 0, timing,
+                         concurrent, s);
+        if (rc) return rc;
+    }
 
     ra::PairArrays a;
     a.q = c.q;
@@ -356,7 +377,7 @@ int run(const Call &c, const rawalign_opts &o) {
     a.first_chunk = c.first_chunk;
     a.bound = c.bound;
     a.reverse = c.reverse ? 1 : 0;
-    const ra::PlanScratch ps = plan_view(*s);
+    const ra::PlanScratch ps = noalloc ? fixed : plan_view(*s);
     const bool tiny = c.bound == ra::kBoundGlobal && !c.reverse;
     if (tiny) {
         rc = get_tiny(*s, c.n_pairs);
@@ -373,7 +394,7 @@ int run(const Call &c, const rawalign_opts &o) {
     }
     if (timing) (void)hipEventRecord(s->ev[1], c.stream);
     hipStream_t st[3] = {c.stream, c.stream, c.stream};
-    if (concurrent) {
+    if (concurrent) {   // never with noalloc (checked above)
         if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         for (int i = 0; i < 3; ++i) {
             st[i] = s->sub[i];
@@ -493,6 +514,16 @@ int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, 
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
            nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
     return run(c, effective_opts(opts));
+}
+
+int rawalign_dtw_batch_noalloc(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
+                               const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
+                               int64_t n_pairs, float *out_score, int32_t *out_end, void *stream) {
+    rawalign_opts o;
+    defaults(o);   // persistent queues, striped kernels, one stream, no timing
+    Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+           nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
+    return run(c, o, true);
 }
 
 int rawalign_dtw_extend(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,

@@ -23,6 +23,8 @@ RAWALIGN_ENOMEM = -3
 RAWALIGN_ENODEV = -4
 RAWALIGN_MAX_REGION = 65536
 RAWALIGN_MAX_QUERY_LONG = 16384
+RAWALIGN_NOALLOC_MAX_PAIRS = 131072
+RAWALIGN_NOALLOC_EDGE_SLOTS = 512
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 LONG_STRIPED = 0
@@ -31,7 +33,8 @@ FLAG_TIMING = 1
 
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
-    "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_extend",
+    "rawalign_opts_default", "rawalign_dtw_batch", "rawalign_dtw_batch_ex", "rawalign_dtw_batch_noalloc",
+    "rawalign_dtw_extend",
     "rawalign_decide", "rawalign_map_bnb", "rawalign_dtw_span", "rawalign_dtw_path", "rawalign_dtw_band",
     "rawalign_dtw_global_batch",
     "rawalign_chain_decide",
@@ -81,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.rawalign_opts_default.argtypes = [ctypes.POINTER(Opts)]
     L.rawalign_dtw_batch.argtypes = pair_args
     L.rawalign_dtw_batch_ex.argtypes = pair_args + [ctypes.POINTER(Opts)]
+    L.rawalign_dtw_batch_noalloc.argtypes = pair_args
     L.rawalign_dtw_extend.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, i64, vp, vp, vp,
                                       ctypes.POINTER(Opts)]
     L.rawalign_decide.argtypes = [vp, i64, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp]
@@ -165,6 +169,11 @@ def rawalign_dtw_batch(q, q_off, q_len, r, r_off, r_len, out_score, out_end, str
 def rawalign_dtw_batch_ex(q, q_off, q_len, r, r_off, r_len, out_score, out_end, opts=None, stream=None):
     _check(load().rawalign_dtw_batch_ex(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
                                         _stream(stream), None if opts is None else ctypes.byref(opts)))
+
+
+def rawalign_dtw_batch_noalloc(q, q_off, q_len, r, r_off, r_len, out_score, out_end, stream=None):
+    _check(load().rawalign_dtw_batch_noalloc(*_pair_args(q, q_off, q_len, r, r_off, r_len, out_score, out_end),
+                                             _stream(stream)))
 
 
 def rawalign_dtw_extend(q, q_off, q_len, r, r_off, r_len, rows, row_off, first_chunk, out_score, out_end,

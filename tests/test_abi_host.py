@@ -124,6 +124,14 @@ def test_argument_errors_without_device(L):
     assert chains(gap_cost=None) == L.RAWALIGN_EINVAL and b"gap_cost" in so.rawalign_last_error()
     assert chains(threshold=float("nan")) == L.RAWALIGN_EINVAL
     assert chains(n_gaps=0, n_chains=0, n_reads=0) == L.RAWALIGN_OK
+    # allocation-free batch: refused beyond its fixed scratch, before any device call
+    big = L.RAWALIGN_NOALLOC_MAX_PAIRS + 1
+    rc = so.rawalign_dtw_batch_noalloc(fake, 10, fake, fake, fake, 10, fake, fake, big, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"exceeds" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_batch_noalloc(fake, 10, fake, fake, fake, 10, fake, fake, -1, fake, fake, None)
+    assert rc == L.RAWALIGN_EINVAL and b"n_pairs" in so.rawalign_last_error()
+    rc = so.rawalign_dtw_batch_noalloc(None, 0, None, None, None, 0, None, None, 0, None, None, None)
+    assert rc == L.RAWALIGN_OK
 
 
 def test_binding_rejects_host_tensors(L):
