@@ -58,22 +58,39 @@ def route_bytes(b):
             "long": int(by[m > 4096].sum())}
 
 
-def cpu_baseline(b, seconds: float):
-    """The CPU oracle (double precision, threaded over pairs) on a random
-    sample of pairs until about `seconds` of work has run."""
+def stratified_order(b, seed: int = 12345, strata: int = 64):
+    """Pairs in an order whose every prefix is spread over the cell-count
+    distribution: pairs sorted by cells, cut into `strata` equal groups, one
+    random pair from each group in turn."""
+    rng = np.random.default_rng(seed)
+    cells = b.q_len.astype(np.int64) * b.r_len.astype(np.int64)
+    groups = [rng.permutation(g) for g in np.array_split(np.argsort(cells, kind="stable"), strata)]
+    order = []
+    for k in range(max(len(g) for g in groups)):
+        order.extend(int(g[k]) for g in groups if k < len(g))
+    return np.array(order, dtype=np.int64)
+
+
+def cpu_baseline(b, seconds: float, gpu_score=None, gpu_end=None):
+    """The CPU oracle (double precision, threaded over pairs) on a sample of
+    pairs spread over the cell-count distribution, until about `seconds` of
+    work has run.  With the GPU's results of the timed step, the same sample
+    also gives their largest relative error against the double oracle and
+    the ends that differ from it (score tolerance 1e-4 relative)."""
     from oracle import oracle
-    rng = np.random.default_rng(12345)
-    order = rng.permutation(b.n_pairs)
+    order = stratified_order(b)
     threads = len(os.sched_getaffinity(0))
     done_cells = 0
     done_pairs = 0
     t0 = time.perf_counter()
     chunk = 64
     used = threads
+    ref = []
     while time.perf_counter() - t0 < seconds and done_pairs < b.n_pairs:
         idx = order[done_pairs:done_pairs + chunk]
         sub = b.subset(idx)
-        _, _, used = oracle.dtw_batch_f64(sub.q, sub.q_off, sub.q_len, sub.r, sub.r_off, sub.r_len, threads)
+        s64, e64, used = oracle.dtw_batch_f64(sub.q, sub.q_off, sub.q_len, sub.r, sub.r_off, sub.r_len, threads)
+        ref.append((idx, s64, e64))
         done_cells += sub.cells
         done_pairs += len(idx)
         chunk = min(chunk * 2, 4096)
@@ -86,10 +103,22 @@ def cpu_baseline(b, seconds: float):
         one_cells += sub.cells
         one_pairs += 1
     dt1 = time.perf_counter() - t1
-    return {"value": done_cells / dt / 1e9, "unit": "GCUPS", "cores": int(used), "kind": "oracle",
-            "sample": f"{done_pairs} random pairs ({done_cells:.3e} cells, {dt:.1f} s), float64 recurrence",
-            "one_core": {"value": one_cells / dt1 / 1e9, "unit": "GCUPS", "cores": 1,
-                         "sample": f"{one_pairs} further pairs ({one_cells:.3e} cells, {dt1:.1f} s)"}}
+    out = {"value": done_cells / dt / 1e9, "unit": "GCUPS", "cores": int(used), "kind": "oracle",
+           "sample": f"{done_pairs} pairs spread over the cell-count distribution ({done_cells:.3e} cells, "
+                     f"{dt:.1f} s), float64 recurrence",
+           "one_core": {"value": one_cells / dt1 / 1e9, "unit": "GCUPS", "cores": 1,
+                        "sample": f"{one_pairs} further pairs ({one_cells:.3e} cells, {dt1:.1f} s)"}}
+    if gpu_score is not None and ref:
+        idx = np.concatenate([x[0] for x in ref])
+        s64 = np.concatenate([x[1] for x in ref])
+        e64 = np.concatenate([x[2] for x in ref])
+        gs = gpu_score[idx].astype(np.float64)
+        rel = np.abs(gs - s64) / np.maximum(np.abs(s64), 1e-30)
+        out["parity"] = {"pairs": int(len(idx)), "max_rel_err": float(rel.max()), "tolerance": 1e-4,
+                         "within_tolerance": bool((np.abs(gs - s64) <= 1e-4 * np.abs(s64) + 1e-6).all()),
+                         "ends_differing_from_f64": int((gpu_end[idx] != e64).sum()),
+                         "of": "the timed (tuned, persistent) step's scores and ends"}
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_multi_uneven_batch_traffic.txt")
@@ -141,23 +170,76 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
-def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3):
+PROBE_OPS = ("v_add_f32", "v_sub_f32", "v_min3_f32", "v_max_f32", "dtw_cell(v_sub,v_min3,v_add|x|)")
+
+
+def valu_rate(iters: int = 20000):
+    """Issue rate of VALU instruction forms on this GPU (libvaluprobe.so):
+    lane-operations per clock per CU for each form at 4 to 32 resident waves
+    per CU, and the shader clock the cycle counter implies.  This is what
+    the roofline's op peak (128 FP32 lane-operations per clock per CU, the
+    datasheet's 157.3 TFLOP/s without the FMA credit) rests on."""
+    import ctypes
+    import torch  # noqa: F401  (loads the HIP runtime first)
+    path = os.path.join(ROOT, "paper_2310_05037_amd", "libvaluprobe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with paper_2310_05037_amd/build.py")
+    L = ctypes.CDLL(path)
+    d = ctypes.c_double
+    L.valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(d), ctypes.POINTER(d),
+                             ctypes.POINTER(d)]
+    out = {"unit": "FP32 lane-operations per clock per CU", "iters": iters, "chains_per_wave": 8, "forms": {}}
+    for op, name in enumerate(PROBE_OPS):
+        row = {}
+        for w in (4, 8, 16, 32):
+            rate, ghz, ms = d(), d(), d()
+            rc = L.valu_probe(op, w, iters, ctypes.byref(rate), ctypes.byref(ghz), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"valu_probe({name}, {w}) failed: {rc}")
+            row[f"{w}_waves_per_cu"] = {"lane_ops_per_clk_per_cu": rate.value, "clock_ghz": ghz.value,
+                                        "kernel_ms": ms.value}
+        out["forms"][name] = row
+    return out
+
+
+def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3, cap_frac: float = 0.5):
     """Read Until serving at a fixed arrival rate, in real time: 400-event
     chunks one second apart, up to 10 chunks and 1-50 candidates per read,
-    resident rows in an 8 GiB arena, two ticks in flight, each a captured
-    graph in which the three route kernels run on their own streams.  A
-    short time-compressed run first warms up the graphs and caches."""
+    30% of the reads off target (decoy candidates only: they never map and
+    stream every chunk), the decision's match bonus set for this data's noise
+    floor (workloads.SYNTHETIC_B_MATCH), resident rows in an 8 GiB arena,
+    three ticks in flight, each a captured graph in which the three route
+    kernels run on their own streams.  A short time-compressed run first
+    warms up the graphs and caches.  The same reads then run again with an
+    arena cap of `cap_frac` of the first run's peak: admission waits
+    (back-pressure), the cap holds, and every read's per-chunk results must
+    equal the first run's."""
     from paper_2310_05037_amd import lib, serve, workloads
     opts = lib.make_opts(streams=streams)
+    bm = workloads.SYNTHETIC_B_MATCH
     warm = workloads.serving_workload(300, rate=rate, seed_index=103)
-    serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120, opts=opts, slots=slots)
+    serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120, opts=opts, slots=slots, b_match=bm)
     wl = workloads.serving_workload(n_reads, rate=rate)
-    _, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600, opts=opts, slots=slots)
-    keep = ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "reads", "ticks", "jobs", "mapped", "unmapped",
-            "failed", "peak_arena_bytes", "wall_s", "gcups", "chunks_per_s", "worst_ms", "tick_device_ms")
+    eng, st = serve.serve(wl, arena_bytes=8 << 30, time_scale=1.0, timeout=600, opts=opts, slots=slots,
+                          b_match=bm)
+    keep = ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "reads", "chunks_per_read", "max_chunks_per_read",
+            "reads_3plus_chunks", "ticks", "jobs", "cells", "mapped", "unmapped", "failed", "peak_arena_bytes",
+            "arena_bytes", "peak_queued_reads", "wall_s", "gcups", "chunks_per_s", "worst_ms", "tick_device_ms")
     out = {k: st[k] for k in keep if k in st}
-    out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period, "streams": streams, "slots": slots,
+    off = sum(1 for rd in wl.reads if rd.true_cand < 0)
+    out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period,
+                "streams": streams, "slots": slots, "off_target_reads": off, "b_match": bm,
+                "threshold": eng.threshold,
                 "latency": "decision on host minus the moment the chunk was available"})
+    cap = int(st["peak_arena_bytes"] * cap_frac) // 4 * 4
+    eng2, st2 = serve.serve(wl, arena_bytes=cap, time_scale=1.0, timeout=600, opts=opts, slots=slots, b_match=bm)
+    same = all(a.status == b.status and len(a.results) == len(b.results) and
+               all(x[:3] == y[:3] and np.array_equal(x[3].view(np.uint32), y[3].view(np.uint32)) and
+                   np.array_equal(x[4], y[4]) for x, y in zip(a.results, b.results))
+               for a, b in zip(eng.reads, eng2.reads))
+    out["capped"] = {k: st2[k] for k in ("p50_ms", "p99_ms", "p999_ms", "max_ms", "chunks", "peak_arena_bytes",
+                                         "arena_bytes", "peak_queued_reads", "failed", "wall_s") if k in st2}
+    out["capped"].update({"cap_fraction_of_uncapped_peak": cap_frac, "results_equal_uncapped": bool(same)})
     return out
 
 
@@ -439,6 +521,72 @@ def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
             "workload": "anchored_chains_100000"}
 
 
+def timed_steps(lib, db, opts, steps: int, warmup: int):
+    """Seconds per call of rawalign_dtw_batch_ex on a DeviceBatch and the mean
+    per-kernel times (HIP events on the streams the kernels run on)."""
+    import torch
+    for _ in range(warmup):
+        db.run(opts=opts)
+    torch.cuda.synchronize()
+    kt = {"plan_ms": [], "lo_ms": [], "hi_ms": [], "long_ms": []}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        db.run(opts=opts)
+        t = lib.rawalign_last_timing()   # waits for this step's events
+        for k in kt:
+            kt[k].append(getattr(t, k))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt / steps, {k: float(np.mean(v)) for k, v in kt.items()}
+
+
+KERNEL_NAMES = {"lo_ms": "k_single<1..8>", "hi_ms": "k_single<9..16>", "long_ms": "k_multi"}
+
+
+def dominant_roofline(b, kt, valu_peak, long_name="k_multi"):
+    """Roofline block of the route kernel with the largest average time."""
+    names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}
+    rc = route_cells(b)
+    dom = max(names, key=lambda k: kt[k])
+    achieved = VALU_OPS_PER_CELL * rc[names[dom]] / (kt[dom] / 1e3)
+    kernel = dict(KERNEL_NAMES, long_ms=long_name)[dom]
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
+            "frac": achieved / valu_peak, "kernel": kernel, "kernel_avg_ms": kt[dom],
+            "kernel_cells": rc[names[dom]], "algorithmic_bytes": route_bytes(b)[names[dom]],
+            "ops_per_cell": VALU_OPS_PER_CELL}
+
+
+def batch_config_leg(lib, b, workload, valu_peak, tuned_extra, steps: int, warmup: int, antidiag: bool = False):
+    """One batch workload timed three or four ways on the same inputs: plain
+    (static assignment, arrival order), persistent with the library
+    defaults, persistent with the tuned settings, and (antidiag) the tuned
+    settings with the anti-diagonal kernel for regions above one stripe.
+    Every form must return the same bits."""
+    import torch
+    db = lib.DeviceBatch(b)
+    forms = [("plain", dict(mode=lib.MODE_PLAIN)), ("persistent_default", {}), ("persistent_tuned", tuned_extra)]
+    if antidiag:
+        forms.append(("antidiag", dict(tuned_extra, long_kernel=lib.LONG_ANTIDIAG)))
+    out = {"workload": workload, "pairs": b.n_pairs, "cells": b.cells, "route_cells": route_cells(b)}
+    ref = None
+    same = True
+    for name, kw in forms:
+        s, kt = timed_steps(lib, db, lib.make_opts(flags=lib.FLAG_TIMING, **kw), steps, warmup)
+        res = db.results()
+        if ref is None:
+            ref = (res[0].copy(), res[1].copy())
+        else:
+            same = same and np.array_equal(res[0].view(np.uint32), ref[0].view(np.uint32)) and \
+                np.array_equal(res[1], ref[1])
+        out[name] = {"value": b.cells / s / 1e9, "unit": "GCUPS", "ms_per_step": s * 1e3, "kernels_ms": kt,
+                     "roofline": dominant_roofline(b, kt, valu_peak,
+                                                   "k_antidiag" if name == "antidiag" else "k_multi")}
+    out["all_forms_bit_identical"] = bool(same)
+    del db
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +596,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-plain", action="store_true", help="time only the tuned path (for profiling runs)")
     ap.add_argument("--skip-anchored", action="store_true", help="leave out the anchor-guided alignment leg")
+    ap.add_argument("--skip-configs", action="store_true",
+                    help="leave out the 4,096-pair plain batch and the long-problem stress legs")
     ap.add_argument("--only-path", action="store_true",
                     help="run only the warping-path leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-banded", action="store_true",
@@ -463,9 +613,14 @@ def main():
                     help="library streams for the serving extension (3: the three route kernels concurrently)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a copy kernel of this size (counter calibration)")
+    ap.add_argument("--valu-rate", action="store_true",
+                    help="only measure the VALU issue rate behind the roofline peak and print it")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.valu_rate:
+        print(json.dumps({"valu_rate": valu_rate()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (pairs are independent: "
@@ -510,28 +665,22 @@ def main():
     plain_opts = lib.make_opts(mode=lib.MODE_PLAIN, flags=lib.FLAG_TIMING)
 
     def timed(opts, steps, warmup):
-        for _ in range(warmup):
-            db.run(opts=opts)
-        torch.cuda.synchronize()
-        kt = {"plan_ms": [], "lo_ms": [], "hi_ms": [], "long_ms": []}
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            db.run(opts=opts)
-            t = lib.rawalign_last_timing()   # waits for this step's events
-            for k in kt:
-                kt[k].append(getattr(t, k))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return dt / steps, {k: float(np.mean(v)) for k, v in kt.items()}
+        return timed_steps(lib, db, opts, steps, warmup)
 
     step_s, kt = timed(tuned, args.steps, args.warmup)
     gcups = cells / step_s / 1e9
+    tuned_score, tuned_end = (x.copy() for x in db.results())
+    checks = {}
     plain_gcups = plain_s = None
     pkt = {}
     variants = {}
     if not args.skip_plain:
         plain_s, pkt = timed(plain_opts, max(2, args.steps // 2), 1)
         plain_gcups = cells / plain_s / 1e9
+        ps, pe = db.results()
+        # The timed (tuned, persistent) step must return the plain step's bits.
+        checks["tuned_equals_plain_all_pairs"] = bool(
+            np.array_equal(tuned_score.view(np.uint32), ps.view(np.uint32)) and np.array_equal(tuned_end, pe))
         # Same batch with the anti-diagonal kernel for the regions above one
         # stripe (the lane-striped kernels keep the shorter ones).
         ad_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_ANTIDIAG)
@@ -550,8 +699,21 @@ def main():
         variants["single_read"] = single_read_leg(lib)
     if not args.skip_anchored:
         variants["banded"] = banded_leg(lib, valu_peak, lib.make_opts(**extra))
+    configs = {}
+    if not args.skip_configs:
+        # the other batch workloads: the 4,096-pair plain batch and the
+        # 1,024 x 10,000 x 20,000 long-problem stress
+        del db
+        torch.cuda.empty_cache()
+        configs["plain_batch_4096"] = batch_config_leg(lib, workloads.plain_batch(), "plain_batch_4096_pairs",
+                                                      valu_peak, extra, steps=10, warmup=2)
+        configs["long_stress_1024"] = batch_config_leg(lib, workloads.long_stress(),
+                                                      "long_stress_1024_x_10000_x_20000", valu_peak, extra,
+                                                      steps=3, warmup=1, antidiag=True)
+        for name, leg in configs.items():
+            checks[f"{name}_forms_bit_identical"] = leg["all_forms_bit_identical"]
 
-    # dominant kernel: the route with the largest average duration
+    # dominant kernel of the timed step: the route with the largest average duration
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}
     dom = max(names, key=lambda k: kt[k])
     dom_cells = rc[names[dom]]
@@ -587,17 +749,26 @@ def main():
         "persistent_over_plain": None if plain_gcups is None else gcups / plain_gcups,
         "kernels_ms": kt,
         "variants": variants,
+        "configs": configs,
+        "checks": checks,
         "roofline": roofline,
         "serving": None,
         "cpu_baseline": None,
     }
-    del db
+    if "db" in locals():
+        del db
     torch.cuda.empty_cache()
     if args.serving_reads > 0:
         out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams, args.serving_slots)
+        checks["serving_capped_results_equal"] = out["serving"]["capped"]["results_equal_uncapped"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds, tuned_score, tuned_end)
+        checks["oracle_sample_within_tolerance"] = out["cpu_baseline"]["parity"]["within_tolerance"]
     print(json.dumps(out), flush=True)
+    failed = [k for k, v in checks.items() if not v]
+    if failed:
+        print(f"bench checks failed: {failed}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

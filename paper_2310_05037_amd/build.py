@@ -25,6 +25,26 @@ HIPCC_FLAGS = [
 ]
 
 
+# Issue-rate probe behind the roofline peak (bench.py --valu-rate); a library
+# of its own, not part of librawalign.
+PROBE_SOURCE = "valu_probe.hip"
+PROBE_LIB = os.path.join(PKG, "libvaluprobe.so")
+
+
+def build_probe(verbose: bool = True) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, "-shared", "-x", "hip", os.path.join(CSRC, PROBE_SOURCE), "-o", tmp]
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if p.returncode != 0:
+        sys.stderr.write("\n".join(ln for ln in p.stdout.splitlines() if "packed-fp32-ops" not in ln) + "\n")
+        raise RuntimeError(f"hipcc failed on {PROBE_SOURCE}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
+
+
 def build(verbose: bool = True, out: str = LIB, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
@@ -54,3 +74,4 @@ def build(verbose: bool = True, out: str = LIB, extra=()) -> str:
 
 if __name__ == "__main__":
     build()
+    build_probe()

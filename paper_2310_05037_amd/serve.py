@@ -150,6 +150,7 @@ class Engine:
         self.jobs = 0
         self.rejected = 0
         self.peak_arena = 0
+        self.peak_pending = 0                # most reads waiting for arena room at once
         self.failed_ticks = 0
         # Backends with launch/poll run up to `slots` ticks at once.
         self.async_backend = hasattr(backend, "launch") and getattr(backend, "slots", 1) > 1
@@ -221,6 +222,7 @@ class Engine:
             self.next_future += 1
             if not st.done:
                 self.pending.append(st)
+        self.peak_pending = max(self.peak_pending, len(self.pending))
         # arrival order: nobody overtakes a read that does not fit yet
         while self.pending:
             st = self.pending[0]
@@ -369,7 +371,10 @@ class Engine:
     def stats(self) -> dict:
         lat = np.array([x[2] for x in self.latencies]) if self.latencies else np.zeros(1)
         st = [s.status for s in self.reads]
+        per_read = np.array([len(s.results) for s in self.reads]) if self.reads else np.zeros(1)
         return {"chunks": len(self.latencies), "reads": len(self.reads), "ticks": self.ticks, "jobs": self.jobs,
+                "chunks_per_read": float(per_read.mean()), "max_chunks_per_read": int(per_read.max()),
+                "reads_3plus_chunks": int((per_read >= 3).sum()), "peak_queued_reads": int(self.peak_pending),
                 "cells": self.cells, "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "p999_ms": float(np.percentile(lat, 99.9) * 1e3),
                 "max_ms": float(lat.max() * 1e3), "mapped": st.count("mapped"), "unmapped": st.count("unmapped"),
@@ -542,11 +547,12 @@ class GpuBackend:
 
 def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_graph: bool = True,
           max_jobs: int = 8192, max_reads: int = 256, timeout: float | None = None, backend=None,
-          slots: int = 3, opts=None):
+          slots: int = 3, opts=None, b_match: float = B_MATCH, threshold: float = SCORE_THRESHOLD):
     """Run a workloads.ServingWorkload through the engine on the GPU.
     time_scale compresses the arrival and chunk clock (0.01: a 1 s chunk
     period becomes 10 ms); slots is the number of ticks in flight; opts
-    (lib.Opts) goes to the extension call.
+    (lib.Opts) goes to the extension call; b_match and threshold are the
+    decision's match bonus and score threshold (Sec. 2.3).
     max_jobs/max_reads size the per-tick tables (a captured tick copies them
     whole); chunks beyond them wait for the next tick."""
     arena_floats = arena_bytes // 4
@@ -560,8 +566,8 @@ def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_gra
     def clock():
         return time.perf_counter() - origin[0]
 
-    eng = Engine(backend, arena_floats, workload.chunk, workload.period * time_scale, max_jobs=max_jobs,
-                 max_reads=max_reads, clock=clock)
+    eng = Engine(backend, arena_floats, workload.chunk, workload.period * time_scale, b_match=b_match,
+                 threshold=threshold, max_jobs=max_jobs, max_reads=max_reads, clock=clock)
     if hasattr(backend, "prepare"):
         backend.prepare(eng.b_match, eng.threshold)   # capture before the clock starts
     for i, rd in enumerate(workload.reads):

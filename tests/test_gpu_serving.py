@@ -111,7 +111,7 @@ def test_extend_alone_equals_mix(L):
         assert torch.equal(rows1, rows_mix[int(row_off[k]):int(row_off[k]) + int(ms[k])])
 
 
-def _oracle_engine(wl):
+def _oracle_engine(wl, b_match=0.4, threshold=20.0):
     from paper_2310_05037_amd import serve
 
     class VClock:
@@ -120,7 +120,8 @@ def _oracle_engine(wl):
         def __call__(self):
             return self.t
     clock = VClock()
-    eng = serve.Engine(OracleBackend(wl.r, 1 << 22), 1 << 22, wl.chunk, wl.period, clock=clock)
+    eng = serve.Engine(OracleBackend(wl.r, 1 << 22), 1 << 22, wl.chunk, wl.period, b_match=b_match,
+                       threshold=threshold, clock=clock)
     for i, rd in enumerate(wl.reads):
         eng.submit(i, rd.arrival, rd.events, rd.r_off, rd.r_len)
     while not eng.all_done():
@@ -149,6 +150,48 @@ def test_serving_loop_matches_oracle_engine(L, use_graph, slots, streams):
         for x, y in zip(a.results, b.results):
             assert x[0] == y[0] and x[1] == y[1] and x[2] == y[2]
             assert np.array_equal(x[3].view(np.uint32), y[3].view(np.uint32)) and np.array_equal(x[4], y[4])
+
+
+def _same_results(eng, ref):
+    for a, b in zip(eng.reads, ref.reads):
+        assert a.status == b.status and len(a.results) == len(b.results), a.rid
+        for x, y in zip(a.results, b.results):
+            assert x[0] == y[0] and x[1] == y[1] and x[2] == y[2]
+            assert np.array_equal(x[3].view(np.uint32), y[3].view(np.uint32)) and np.array_equal(x[4], y[4])
+
+
+def test_serving_streams_chunks_and_binds_memory_cap(L):
+    """Reads stream several chunks through the captured ticks: half the
+    reads are off target (decoy candidates only, so they never map and run
+    to their last chunk) and the match bonus is set for this data's noise
+    floor.  Every chunk of every read equals the oracle-backed engine bit
+    for bit, with resident rows carried across chunks.  A second run with an
+    arena cap of half the first run's peak makes admission wait (reads
+    queue), never exceeds the cap, and gives the same results."""
+    from paper_2310_05037_amd import serve
+    wl = W.serving_workload(48, rate=200.0, chunk=400, max_chunks=5, max_cands=8, ref_bases=200_000,
+                            period=1.0, seed_index=34, off_target=0.5)
+    bm = W.SYNTHETIC_B_MATCH
+    _say(f"  gpu: serving multi-chunk reads={len(wl.reads)} b_match={bm}")
+    eng, st = serve.serve(wl, arena_bytes=64 << 20, time_scale=0.02, use_graph=True, max_jobs=1024,
+                          max_reads=128, timeout=120, slots=3, opts=L.make_opts(streams=3), b_match=bm)
+    print("serving multi-chunk", {k: st[k] for k in ("chunks", "chunks_per_read", "max_chunks_per_read",
+                                                      "reads_3plus_chunks", "mapped", "unmapped",
+                                                      "peak_arena_bytes", "peak_queued_reads")})
+    ref = _oracle_engine(wl, b_match=bm)
+    assert st["failed"] == 0 and st["reads_3plus_chunks"] >= 8 and st["unmapped"] >= 10 and st["mapped"] >= 10
+    assert all(len(rd.results) > 1 for rd, w in zip(eng.reads, wl.reads) if w.true_cand < 0 and
+               len(w.events) > wl.chunk)
+    _same_results(eng, ref)
+    need = max(int(rd.r_len.sum()) for rd in wl.reads) * 4
+    cap = max(st["peak_arena_bytes"] // 2, need)
+    assert cap < st["peak_arena_bytes"]
+    _say(f"  gpu: serving under a cap of {cap} bytes (uncapped peak {st['peak_arena_bytes']})")
+    eng2, st2 = serve.serve(wl, arena_bytes=cap, time_scale=0.02, use_graph=True, max_jobs=1024, max_reads=128,
+                            timeout=120, slots=3, opts=L.make_opts(streams=3), b_match=bm)
+    print("serving capped", {k: st2[k] for k in ("peak_arena_bytes", "arena_bytes", "peak_queued_reads")})
+    assert st2["failed"] == 0 and st2["peak_arena_bytes"] <= cap and st2["peak_queued_reads"] > 0
+    _same_results(eng2, ref)
 
 
 def test_extend_edge_cases(L):
