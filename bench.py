@@ -39,23 +39,31 @@ FP32_VECTOR_PEAK = 157.3e12    # datasheet FP32 vector FLOP/s (credits FMA and p
 FLOPS_PER_CELL = 5             # sub, abs, 2 x min, add
 
 
-def route_cells(b):
-    """Cells per kernel route (same routing as the library's planner)."""
+EDGE_CAP = 16384   # RAWALIGN_MAX_QUERY_LONG: longer queries keep one stripe up to 4096 levels
+
+
+def route_masks(b, single_max: int = 4096):
+    """Pairs per kernel route, as the library's planner routes them: up to
+    2048 levels, up to the single-stripe cut-off (single_max, and up to 4096
+    levels for queries too long for a stripe edge column), longer."""
     m = b.r_len.astype(np.int64)
-    cells = b.q_len.astype(np.int64) * m
+    n = b.q_len.astype(np.int64)
     lo = m <= 2048
-    hi = (m > 2048) & (m <= 4096)
-    long_ = m > 4096
-    return {"lo": int(cells[lo].sum()), "hi": int(cells[hi].sum()), "long": int(cells[long_].sum())}
+    hi = ~lo & ((m <= single_max) | ((m <= 4096) & (n > EDGE_CAP)))
+    return {"lo": lo, "hi": hi, "long": ~lo & ~hi}
 
 
-def route_bytes(b):
+def route_cells(b, single_max: int = 4096):
+    """Cells per kernel route."""
+    cells = b.q_len.astype(np.int64) * b.r_len.astype(np.int64)
+    return {k: int(cells[v].sum()) for k, v in route_masks(b, single_max).items()}
+
+
+def route_bytes(b, single_max: int = 4096):
     """Algorithmic HBM bytes per route: every pair reads its query and region
     once and writes a score and an end (4n + 4m + 8)."""
-    m = b.r_len.astype(np.int64)
-    by = 4 * b.q_len.astype(np.int64) + 4 * m + 8
-    return {"lo": int(by[m <= 2048].sum()), "hi": int(by[(m > 2048) & (m <= 4096)].sum()),
-            "long": int(by[m > 4096].sum())}
+    by = 4 * b.q_len.astype(np.int64) + 4 * b.r_len.astype(np.int64) + 8
+    return {k: int(by[v].sum()) for k, v in route_masks(b, single_max).items()}
 
 
 def stratified_order(b, seed: int = 12345, strata: int = 64):
@@ -202,20 +210,26 @@ def valu_rate(iters: int = 20000):
     return out
 
 
-def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3, cap_frac: float = 0.5):
+def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3, cap_frac: float = 0.5,
+                pipe_waves: int = 8, single_max: int = 2048):
     """Read Until serving at a fixed arrival rate, in real time: 400-event
     chunks one second apart, up to 10 chunks and 1-50 candidates per read,
     30% of the reads off target (decoy candidates only: they never map and
     stream every chunk), the decision's match bonus set for this data's noise
     floor (workloads.SYNTHETIC_B_MATCH), resident rows in an 8 GiB arena,
     three ticks in flight, each a captured graph in which the three route
-    kernels run on their own streams.  A short time-compressed run first
-    warms up the graphs and caches.  The same reads then run again with an
+    kernels run on their own streams, regions above `single_max` levels
+    shared by `pipe_waves` waves each (the pipelined kernel; 0: one wave per
+    pair).  A short time-compressed run first warms up the graphs and
+    caches.  The same reads then run again with an
     arena cap of `cap_frac` of the first run's peak: admission waits
     (back-pressure), the cap holds, and every read's per-chunk results must
     equal the first run's."""
     from paper_2310_05037_amd import lib, serve, workloads
-    opts = lib.make_opts(streams=streams)
+    kw = dict(streams=streams, single_max=single_max)
+    if pipe_waves:
+        kw.update(long_kernel=lib.LONG_PIPELINE, pipe_waves=pipe_waves)
+    opts = lib.make_opts(**kw)
     bm = workloads.SYNTHETIC_B_MATCH
     warm = workloads.serving_workload(300, rate=rate, seed_index=103)
     serve.serve(warm, arena_bytes=1 << 30, time_scale=0.05, timeout=120, opts=opts, slots=slots, b_match=bm)
@@ -228,7 +242,8 @@ def serving_leg(n_reads: int, rate: float, streams: int = 3, slots: int = 3, cap
     out = {k: st[k] for k in keep if k in st}
     off = sum(1 for rd in wl.reads if rd.true_cand < 0)
     out.update({"rate_reads_per_s": rate, "chunk_events": wl.chunk, "chunk_period_s": wl.period,
-                "streams": streams, "slots": slots, "off_target_reads": off, "b_match": bm,
+                "streams": streams, "slots": slots, "opts": {k: v for k, v in kw.items()},
+                "off_target_reads": off, "b_match": bm,
                 "threshold": eng.threshold,
                 "latency": "decision on host minus the moment the chunk was available"})
     cap = int(st["peak_arena_bytes"] * cap_frac) // 4 * 4
@@ -543,20 +558,21 @@ def timed_steps(lib, db, opts, steps: int, warmup: int):
 KERNEL_NAMES = {"lo_ms": "k_single<1..8>", "hi_ms": "k_single<9..16>", "long_ms": "k_multi"}
 
 
-def dominant_roofline(b, kt, valu_peak, long_name="k_multi"):
+def dominant_roofline(b, kt, valu_peak, long_name="k_multi", single_max: int = 4096):
     """Roofline block of the route kernel with the largest average time."""
     names = {"lo_ms": "lo", "hi_ms": "hi", "long_ms": "long"}
-    rc = route_cells(b)
+    rc = route_cells(b, single_max)
     dom = max(names, key=lambda k: kt[k])
     achieved = VALU_OPS_PER_CELL * rc[names[dom]] / (kt[dom] / 1e3)
     kernel = dict(KERNEL_NAMES, long_ms=long_name)[dom]
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
             "frac": achieved / valu_peak, "kernel": kernel, "kernel_avg_ms": kt[dom],
-            "kernel_cells": rc[names[dom]], "algorithmic_bytes": route_bytes(b)[names[dom]],
+            "kernel_cells": rc[names[dom]], "algorithmic_bytes": route_bytes(b, single_max)[names[dom]],
             "ops_per_cell": VALU_OPS_PER_CELL}
 
 
-def batch_config_leg(lib, b, workload, valu_peak, tuned_extra, steps: int, warmup: int, antidiag: bool = False):
+def batch_config_leg(lib, b, workload, valu_peak, tuned_extra, steps: int, warmup: int, antidiag: bool = False,
+                     pipeline: bool = False):
     """One batch workload timed three or four ways on the same inputs: plain
     (static assignment, arrival order), persistent with the library
     defaults, persistent with the tuned settings, and (antidiag) the tuned
@@ -564,10 +580,22 @@ def batch_config_leg(lib, b, workload, valu_peak, tuned_extra, steps: int, warmu
     Every form must return the same bits."""
     import torch
     db = lib.DeviceBatch(b)
-    forms = [("plain", dict(mode=lib.MODE_PLAIN)), ("persistent_default", {}), ("persistent_tuned", tuned_extra)]
+    forms = [("plain", dict(mode=lib.MODE_PLAIN)), ("persistent_default", {})]
+    if tuned_extra:
+        forms.append(("persistent_tuned_on_uneven_batch", tuned_extra))
     if antidiag:
-        forms.append(("antidiag", dict(tuned_extra, long_kernel=lib.LONG_ANTIDIAG)))
-    out = {"workload": workload, "pairs": b.n_pairs, "cells": b.cells, "route_cells": route_cells(b)}
+        forms.append(("antidiag", dict(long_kernel=lib.LONG_ANTIDIAG)))
+    if pipeline:
+        for w in (2, 4, 8):
+            forms.append((f"pipeline_{w}_waves", dict(long_kernel=lib.LONG_PIPELINE, pipe_waves=w)))
+    # the autotuner on this batch itself
+    t0 = time.perf_counter()
+    best = lib.rawalign_autotune(*db.args())
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    self_tuned = {k: v for k, v in best.as_dict().items() if k != "flags"}
+    forms.append(("persistent_tuned", self_tuned))
+    out = {"workload": workload, "pairs": b.n_pairs, "cells": b.cells, "route_cells": route_cells(b),
+           "tuned_opts": self_tuned, "autotune_ms": tune_ms}
     ref = None
     same = True
     for name, kw in forms:
@@ -578,9 +606,11 @@ def batch_config_leg(lib, b, workload, valu_peak, tuned_extra, steps: int, warmu
         else:
             same = same and np.array_equal(res[0].view(np.uint32), ref[0].view(np.uint32)) and \
                 np.array_equal(res[1], ref[1])
+        kind = kw.get("long_kernel", 0)
         out[name] = {"value": b.cells / s / 1e9, "unit": "GCUPS", "ms_per_step": s * 1e3, "kernels_ms": kt,
                      "roofline": dominant_roofline(b, kt, valu_peak,
-                                                   "k_antidiag" if name == "antidiag" else "k_multi")}
+                                                   {1: "k_antidiag", 2: "k_pipe"}.get(kind, "k_multi"),
+                                                   kw.get("single_max") or 4096)}
     out["all_forms_bit_identical"] = bool(same)
     del db
     torch.cuda.empty_cache()
@@ -602,6 +632,8 @@ def main():
                     help="run only the warping-path leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-banded", action="store_true",
                     help="run only the banded-DTW leg and print its JSON (for profiling runs)")
+    ap.add_argument("--only-configs", action="store_true",
+                    help="run only the 4,096-pair plain batch and long-stress legs (library defaults) and print them")
     ap.add_argument("--only-anchored", action="store_true",
                     help="run only the anchor-guided alignment leg and print its JSON (for profiling runs)")
     ap.add_argument("--opts", type=str, default="", help="JSON dict of rawalign_opts fields for the tuned path")
@@ -611,6 +643,10 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=3, help="serving ticks in flight")
     ap.add_argument("--serving-streams", type=int, default=3, choices=(1, 3),
                     help="library streams for the serving extension (3: the three route kernels concurrently)")
+    ap.add_argument("--serving-pipe-waves", type=int, default=8, choices=(0, 2, 4, 8),
+                    help="waves sharing each long region in the serving extension (0: one wave per pair)")
+    ap.add_argument("--serving-single-max", type=int, default=2048, choices=(2048, 4096),
+                    help="widest region swept as one stripe in the serving extension")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a copy kernel of this size (counter calibration)")
     ap.add_argument("--valu-rate", action="store_true",
@@ -641,13 +677,20 @@ def main():
     if args.only_path:
         print(json.dumps({"path": path_leg(lib, workloads.uneven_batch(), None, steps=args.steps)}), flush=True)
         return
+    if args.only_configs:
+        legs = {"plain_batch_4096": batch_config_leg(lib, workloads.plain_batch(), "plain_batch_4096_pairs",
+                                                     valu_peak, {}, steps=10, warmup=2),
+                "long_stress_1024": batch_config_leg(lib, workloads.long_stress(), "long_stress_1024_x_10000_x_20000",
+                                                     valu_peak, {}, steps=args.steps, warmup=1, antidiag=True,
+                                                     pipeline=True)}
+        print(json.dumps({"configs": legs}), flush=True)
+        return
     if args.only_banded:
         print(json.dumps({"banded": banded_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
         return
 
     b = workloads.uneven_batch()
     cells = b.cells
-    rc = route_cells(b)
     db = lib.DeviceBatch(b)
     stream = torch.cuda.current_stream()
 
@@ -659,9 +702,11 @@ def main():
         t0 = time.perf_counter()
         best = lib.rawalign_autotune(*db.args())
         tune_ms = (time.perf_counter() - t0) * 1e3
-        extra = {k: getattr(best, k) for k in ("mode", "long_kernel", "lo_waves_per_cu", "hi_waves_per_cu",
-                                               "long_waves_per_cu", "streams")}
+        extra = {k: v for k, v in best.as_dict().items() if k != "flags"}
     tuned = lib.make_opts(flags=lib.FLAG_TIMING, **extra)
+    single_max = int(extra.get("single_max") or 4096)
+    rc = route_cells(b, single_max)
+    long_name = {1: "k_antidiag", 2: "k_pipe"}.get(int(extra.get("long_kernel", 0)), "k_multi")
     plain_opts = lib.make_opts(mode=lib.MODE_PLAIN, flags=lib.FLAG_TIMING)
 
     def timed(opts, steps, warmup):
@@ -686,8 +731,18 @@ def main():
         ad_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_ANTIDIAG)
         ad_s, akt = timed(ad_opts, 2, 1)
         variants["long_antidiag"] = {"value": cells / ad_s / 1e9, "unit": "GCUPS", "ms_per_step": ad_s * 1e3,
-                                     "kernels_ms": akt, "long_route_gcups": rc["long"] / akt["long_ms"] / 1e6,
+                                     "kernels_ms": akt,
+                                     "long_route_gcups": route_cells(b)["long"] / akt["long_ms"] / 1e6,
                                      "kernel": "k_antidiag"}
+        # Same batch with the regions above one stripe shared by 4 waves each
+        # (pipelined stripes), at the tuned cut-off.
+        pp_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_PIPELINE, pipe_waves=4,
+                                single_max=single_max)
+        pp_s, pkt4 = timed(pp_opts, 3, 1)
+        variants["long_pipeline_4_waves"] = {"value": cells / pp_s / 1e9, "unit": "GCUPS",
+                                             "ms_per_step": pp_s * 1e3, "kernels_ms": pkt4,
+                                             "long_route_gcups": rc["long"] / pkt4["long_ms"] / 1e6,
+                                             "kernel": "k_pipe", "single_max": single_max}
 
     if not args.skip_plain:
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
@@ -709,7 +764,7 @@ def main():
                                                       valu_peak, extra, steps=10, warmup=2)
         configs["long_stress_1024"] = batch_config_leg(lib, workloads.long_stress(),
                                                       "long_stress_1024_x_10000_x_20000", valu_peak, extra,
-                                                      steps=3, warmup=1, antidiag=True)
+                                                      steps=3, warmup=1, antidiag=True, pipeline=True)
         for name, leg in configs.items():
             checks[f"{name}_forms_bit_identical"] = leg["all_forms_bit_identical"]
 
@@ -721,8 +776,8 @@ def main():
     traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
                 "frac": achieved / valu_peak, "traffic": traffic,
-                "algorithmic_bytes": route_bytes(b)[names[dom]],
-                "kernel": {"lo_ms": "k_single<1..8>", "hi_ms": "k_single<9..16>", "long_ms": "k_multi"}[dom],
+                "algorithmic_bytes": route_bytes(b, single_max)[names[dom]],
+                "kernel": dict(KERNEL_NAMES, long_ms=long_name)[dom],
                 "kernel_avg_ms": kt[dom], "kernel_cells": dom_cells,
                 "ops_per_cell": VALU_OPS_PER_CELL,
                 "whole_step_frac": gcups * 1e9 * VALU_OPS_PER_CELL / valu_peak,
@@ -759,7 +814,8 @@ def main():
         del db
     torch.cuda.empty_cache()
     if args.serving_reads > 0:
-        out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams, args.serving_slots)
+        out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams, args.serving_slots,
+                                     pipe_waves=args.serving_pipe_waves, single_max=args.serving_single_max)
         checks["serving_capped_results_equal"] = out["serving"]["capped"]["results_equal_uncapped"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds, tuned_score, tuned_end)

@@ -69,10 +69,13 @@ extern "C" {
 #define RAWALIGN_MODE_PLAIN 0       /* one workgroup per pair in arrival order, fixed grids */
 #define RAWALIGN_MODE_PERSISTENT 1  /* device-sized grids, atomic work queues, longest pairs first */
 
-/* Kernels for regions longer than one stripe (4096 levels). */
+/* Kernels for regions longer than one stripe (above opts.single_max levels). */
 #define RAWALIGN_LONG_STRIPED 0     /* one wave sweeps the stripes in turn, edges through device memory */
 #define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup per pair sweeps anti-diagonals of 256-row blocks through LDS;
                                        plain batches only (rawalign_dtw_extend rejects it) */
+#define RAWALIGN_LONG_PIPELINE 2    /* opts.pipe_waves waves share each pair, one stripe each in turn, the
+                                       stripes pipelined: a stripe starts as soon as its left neighbour has
+                                       stored the edge rows it needs (waits on LDS counters, no barriers) */
 
 /* opts.flags */
 #define RAWALIGN_FLAG_TIMING 1      /* record hipEvents around every kernel (rawalign_last_timing) */
@@ -86,10 +89,17 @@ typedef struct rawalign_opts {
     int32_t streams;            /* 1: the three kernels run one after another on `stream`;
                                    3: concurrently on internal streams joined back to `stream` */
     int32_t flags;              /* RAWALIGN_FLAG_* */
+    int32_t single_max;         /* widest region (levels) swept as one stripe: 2048 or 4096 (0 = 4096).  Regions
+                                   of 2049..4096 levels then take one stripe of 34..64 columns per lane (two
+                                   waves per SIMD) or two stripes of 17..32 (four waves per SIMD); a query longer
+                                   than RAWALIGN_MAX_QUERY_LONG keeps one stripe either way */
+    int32_t pipe_waves;         /* RAWALIGN_LONG_PIPELINE: waves per workgroup sharing a pair, 2, 4 or 8 (0 = 4);
+                                   long_waves_per_cu then counts waves of that kernel per CU */
 } rawalign_opts;
 
 /* Fill `opts` with the library defaults (persistent mode, striped long
- * kernel, occupancy-sized grids, one stream).  Returns RAWALIGN_OK. */
+ * kernel, occupancy-sized grids, one stream, single stripes up to 4096
+ * levels).  Returns RAWALIGN_OK. */
 int rawalign_opts_default(rawalign_opts *opts);
 
 /*
@@ -392,13 +402,24 @@ int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *
                           uint8_t *out_mapped, void *stream);
 
 /*
- * Autotuner: times candidate settings (persistent grid sizes of the three
- * kernels, concurrent or sequential kernels) on the caller's device batch
- * (same layout as rawalign_dtw_batch; out_score/out_end are scratch outputs)
- * and keeps the fastest as this device's tuned setting.  If cache_path is not
- * NULL the result is also written there as JSON keyed by device name, gfx
- * architecture and library version.  `best` (host, may be NULL) receives it.
- * Synchronises `stream`.
+ * Autotuner: times candidate settings of rawalign_dtw_batch_ex on the
+ * caller's device batch (same layout as rawalign_dtw_batch; out_score and
+ * out_end are scratch outputs) and keeps the fastest as this device's tuned
+ * setting, which opts == NULL then selects.  Two stages, each candidate one
+ * warm-up call and the mean of three:
+ *   1. the kernel shape: the single-stripe cut-off (single_max 4096 or 2048,
+ *      i.e. 34..64 columns per lane on one stripe or 17..32 on two for
+ *      regions of 2049..4096 levels) times the long-route kernel and its
+ *      workgroup shape (one wave per pair, or 2, 4 or 8 waves sharing each
+ *      pair: RAWALIGN_LONG_PIPELINE);
+ *   2. at that shape: one or three streams, and each route's persistent grid
+ *      at or below its occupancy limit.
+ * Every candidate returns the same bits, so the choice affects time only.
+ * If cache_path is not NULL the result is also written there as JSON keyed
+ * by device name, gfx architecture and library version (rawalign_load_tuning
+ * reads it back).  `best` (host, may be NULL) receives it.  The batch should
+ * have the size distribution of the work to come (the tuner measures, it
+ * does not model).  Synchronises `stream`.
  */
 int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                       const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,

@@ -13,7 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librawalign.so")
 
 SOURCES = ["dtw_single.hip", "dtw_multi.hip", "dtw_antidiag.hip", "dtw_plan.hip", "dtw_bnb.hip", "dtw_global.hip",
-           "dtw_band.hip", "dtw_path.hip", "dtw_noalloc.hip", "rawalign_abi.cpp"]
+           "dtw_band.hip", "dtw_path.hip", "dtw_noalloc.hip", "dtw_pipe.hip",
+           "rawalign_abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

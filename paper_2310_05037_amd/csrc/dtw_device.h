@@ -303,6 +303,26 @@ RA_DEV void two_steps2(int t, int n, int lane, const float (&rv)[C], float (&A)[
     if (EOUT && t >= 126 && t - 126 < n && lane == 63) edge[t - 126] = A[C - 1];
 }
 
+// Cross-wave hand-over hook of the sweep (the multi-wave pipeline,
+// dtw_pipe.hip).  NoSync, the default, is compiled out entirely.  An active
+// policy is called every kBlock steps of the sweep:
+//   wait(rows):     before the edge values of rows < rows are loaded (the
+//                   stripe to the left must have stored them); false after a
+//                   time-out, and the sweep then runs on without waiting;
+//   publish(rows):  after this stripe's lane 63 has stored the edge values of
+//                   rows < rows;
+//   set_corner(v):  this stripe's row -1 value in its last column, handed
+//                   to the next stripe before any row is published;
+//   corner():       the corner left of this stripe, read after the first wait.
+struct NoSync {
+    static constexpr bool kActive = false;
+    static constexpr int kBlock = 64;
+    RA_DEV bool wait(int) { return true; }
+    RA_DEV void publish(int) {}
+    RA_DEV void set_corner(float) {}
+    RA_DEV float corner() { return 0.0f; }
+};
+
 // One column stripe [col_base, col_base + 64*C) of a pair on one wave.
 // Returns this stripe's (min, argmin) of row n-1 over columns < m.  ILP2:
 // two independent chains per lane and step (lane skew 2, see row_step2),
@@ -311,14 +331,18 @@ RA_DEV void two_steps2(int t, int n, int lane, const float (&rv)[C], float (&A)[
 //   next_corner: receives D(-1, col_base+64C-1) for the next stripe.  Both
 //                travel in registers because the resident row is updated in
 //                place, stripe by stripe.
-template <int C, bool EXT, bool EIN, bool EOUT, bool ILP2>
+template <int C, bool EXT, bool EIN, bool EOUT, bool ILP2, class SYNC = NoSync>
 RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, float &next_corner, float &best,
-                  int &bj) {
+                  int &bj, SYNC *sync = nullptr) {
+    static_assert(!SYNC::kActive || !ILP2, "the hand-over assumes a skew of one lane per step");
     const int lane = opaque_lane();
     const int col0 = col_base + lane * C;
     float rv[C], A[C], B[C];
     load_lane<C, EXT>(pv, col0, rv, A, B);
     next_corner = __shfl(A[C - 1], 63, 64);
+    if constexpr (SYNC::kActive) {
+        if (EOUT) sync->set_corner(next_corner);
+    }
     const int n = pv.n;
     if (n > 0) {
         // Left boundary of the region: D(i,-1) = +inf for every row.  At row
@@ -340,12 +364,36 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
         float qa = uload(qrs, 0, nm1, qrev), qb = uload(qrs, 1, nm1, qrev);
         float ea = 0.0f, eb = 0.0f;
         if (EIN) {
+            if constexpr (SYNC::kActive) {
+                // rows [0, kBlock + 2) before the first loads; the corner
+                // was handed over before any row was published
+                (void)sync->wait(n < SYNC::kBlock + 2 ? n : SYNC::kBlock + 2);
+                E1 = sync->corner();
+            }
             ea = uload(ers, 0, nm1);
             eb = uload(ers, 1, nm1);
         }
         int t = 0;
+        // Every kBlock steps: wait for the edge rows the next kBlock steps
+        // load (up to t + kBlock + 1) and publish the rows lane 63 has
+        // stored (it stores row u - 63 at step u, so steps 0 .. t-1 stored
+        // rows 0 .. t-64).
+#define RA_SYNC_POINT                                                                        \
+    if constexpr (SYNC::kActive) {                                                           \
+        if ((t & (SYNC::kBlock - 1)) == 0) {                                                 \
+            if (EIN) {                                                                       \
+                const int need = t + SYNC::kBlock + 2;                                       \
+                (void)sync->wait(need < n ? need : n);                                       \
+            }                                                                                \
+            if (EOUT) {                                                                      \
+                const int done = t - 63;                                                     \
+                sync->publish(done < 0 ? 0 : (done < n ? done : n));                         \
+            }                                                                                \
+        }                                                                                    \
+    }
 #define RA_STEPS(MASKED)                                                                     \
     {                                                                                        \
+        RA_SYNC_POINT                                                                        \
         const float q0 = qa, q1 = qb, e0 = ea, e1 = eb;                                      \
         qa = uload(qrs, t + 2, nm1, qrev);                                                   \
         qb = uload(qrs, t + 3, nm1, qrev);                                                   \
@@ -362,19 +410,22 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
         for (; t < tb; t += 2) RA_STEPS(false)
         for (; t < T; t += 2) RA_STEPS(true)
 #undef RA_STEPS
+#undef RA_SYNC_POINT
+        if constexpr (SYNC::kActive) {
+            if (EOUT) sync->publish(n);   // every edge row is stored
+        }
     }
     finish_lane<C, EXT>(pv, col0, A, best, bj);
     wave_min(best, bj);
 }
 
 // Stripe shape of a region of m levels: S stripes of 64*C columns,
-// C = step h (step: kSingleColStep or kMultiColStep).  Single-stripe pairs
-// use the smallest h with 64 C >= m.  Multi-stripe pairs use
-// S = ceil(m / (256 kMultiMaxK)) and the smallest h with S * 64 C >= m; then
-// every stripe starts inside the region ((S-1)*64*C < m over the whole
-// range of m).  Returns the padded columns of one stripe, 64 C.
-RA_DEV int stripe_shape(int m, int &S, int &h) {
-    const bool single = m <= kSingleMaxRegion;
+// C = step h.  single: the pair is on a single-stripe route (one stripe,
+// the smallest h with 64 C >= m, step kSingleColStep).  Otherwise S =
+// ceil(m / (256 kMultiMaxK)) and the smallest h with S * 64 C >= m, step
+// kMultiColStep; then every stripe starts inside the region ((S-1)*64*C < m
+// over the whole range of m).  Returns the padded columns of one stripe, 64 C.
+RA_DEV int stripe_shape(int m, int &S, int &h, bool single) {
     const int width = single ? kSingleMaxRegion : 256 * kMultiMaxK;
     const int group = 64 * (single ? kSingleColStep : kMultiColStep);
     S = (m + width - 1) / width;
@@ -382,6 +433,22 @@ RA_DEV int stripe_shape(int m, int &S, int &h) {
     h = (m + group * S - 1) / (group * S);
     return group * h;
 }
+
+// Narrowest and widest multi-stripe lanes: the smallest h over every region
+// that can take the multi-stripe route (above the lowest single-stripe
+// cut-off, 2048 levels, up to kMaxRegion), and 4 kMultiMaxK / step.
+constexpr int multi_min_h() {
+    int hmin = 4 * kMultiMaxK / kMultiColStep;
+    for (int m = kSingleLoMaxRegion + 1; m <= kMaxRegion; ++m) {
+        const int w = 256 * kMultiMaxK;
+        const int S = (m + w - 1) / w;
+        const int h = (m + 64 * kMultiColStep * S - 1) / (64 * kMultiColStep * S);
+        if (h < hmin) hmin = h;
+    }
+    return hmin;
+}
+constexpr int kMultiMinH = multi_min_h();
+constexpr int kMultiMaxH = 4 * kMultiMaxK / kMultiColStep;
 
 // Two independent min-plus chains per lane (the lane's two column halves one
 // row apart); the skew per stripe grows from 64 to 128 steps.  Off by

@@ -14,21 +14,6 @@ constexpr int kMultiWaves = RA_MULTI_WAVES;
 constexpr int kMultiWaves = kMultiMaxK <= 8 ? 4 : (kMultiMaxK <= 12 ? 3 : 2);
 #endif
 
-// Narrowest stripe any region above one stripe gets from stripe_shape: the
-// smallest h = ceil(m / (128 S)) over m in (kSingleMaxRegion, kMaxRegion].
-constexpr int multi_min_h() {
-    int hmin = 4 * kMultiMaxK / kMultiColStep;
-    for (int m = kSingleMaxRegion + 1; m <= kMaxRegion; ++m) {
-        const int w = 256 * kMultiMaxK;
-        const int S = (m + w - 1) / w;
-        const int h = (m + 64 * kMultiColStep * S - 1) / (64 * kMultiColStep * S);
-        if (h < hmin) hmin = h;
-    }
-    return hmin;
-}
-constexpr int kMultiMinH = multi_min_h();
-constexpr int kMultiMaxH = 4 * kMultiMaxK / kMultiColStep;
-
 // Columns per lane C = 2H for every H in [kMultiMinH, kMultiMaxH].
 template <int H, bool EXT>
 RA_DEV void multi_dispatch(int h, const PairView &pv, int S, float *edge, float &best, int &bj) {
@@ -56,7 +41,7 @@ void k_multi(PairArrays a, const int32_t *__restrict__ list, const int32_t *__re
         const int p = list[item];
         const PairView pv = pair_view<EXT>(a, p);
         int S, h;
-        stripe_shape(pv.m, S, h);
+        stripe_shape(pv.m, S, h, false);
         float best = __builtin_nanf("");
         int bj = -2;
         multi_dispatch<kMultiMinH, EXT>(h, pv, S, edge, best, bj);

@@ -9,6 +9,7 @@ struct PlanArgs {
     int64_t n_pairs;
     int buckets;      // 1: single bucket (plain), kBuckets: LPT buckets
     int extend;
+    int single_max;   // widest region of the single-stripe routes
     PlanScratch s;
     const int32_t *band;   // banded planning (band half-width per pair), else null
 };
@@ -93,9 +94,12 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
         end = -1;
         return -1;
     }
+    // Single-stripe routes up to the cut-off; regions up to the widest
+    // single stripe whose query is too long for a stripe edge column keep
+    // one stripe whatever the cut-off, so the result never depends on it.
     int route;
     if (m <= kSingleLoMaxRegion) route = kRouteSingleLo;
-    else if (m <= kSingleMaxRegion) route = kRouteSingleHi;
+    else if (m <= pa.single_max || (m <= kSingleMaxRegion && n > kEdgeCap)) route = kRouteSingleHi;
     else route = kRouteMulti;
     bucket = 0;
     if (pa.buckets > 1) {
@@ -103,7 +107,7 @@ RA_DEV int classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, in
         // cells (n + 64 steps per stripe x the stripe's padded columns),
         // bucket 0 holding the largest pairs.
         int S, h;
-        const int cols = stripe_shape(m, S, h);
+        const int cols = stripe_shape(m, S, h, route != kRouteMulti);
         const float work = (float)(n + 64) * (float)(S * cols) + 1.0f;
         int b = (int)(4.0f * __log2f(work));
         b = b < 0 ? 0 : (b >= pa.buckets ? pa.buckets - 1 : b);
@@ -228,6 +232,7 @@ hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cf
     pa.n_pairs = n_pairs;
     pa.buckets = cfg.persistent ? kBuckets : 1;
     pa.extend = a.rows != nullptr;
+    pa.single_max = cfg.single_max;
     pa.s = s;
     pa.band = nullptr;
     return run_plan(pa, stream);
@@ -240,6 +245,7 @@ hipError_t launch_band_plan(const PairArrays &a, const int32_t *band, int64_t n_
     pa.n_pairs = n_pairs;
     pa.buckets = kBuckets;
     pa.extend = 0;
+    pa.single_max = kSingleMaxRegion;
     pa.s = s;
     pa.band = band;
     return run_plan(pa, stream);

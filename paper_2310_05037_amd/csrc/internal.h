@@ -146,9 +146,14 @@ struct LaunchCfg {
     bool persistent;    // atomic queue + LPT order (else static assignment, arrival order)
     int lo_grid;        // grid sizes (workgroups of one wave)
     int hi_grid;
-    int multi_grid;     // also the number of edge slots
+    int multi_grid;     // workgroups of the multi-stripe route (one wave, or pipe_waves in the pipeline); also
+                        // the number of edge slots
     int antidiag_grid;  // workgroups of the anti-diagonal kernel (256 threads)
+    int single_max = kSingleMaxRegion;   // widest region of the single-stripe routes (2048 or 4096)
 };
+
+// Waves sharing a pair in the pipelined multi-stripe kernel (dtw_pipe.hip).
+constexpr int kPipeMaxWaves = 8;
 
 hipError_t launch_plan(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
                        const PlanScratch &s, hipStream_t stream);
@@ -160,6 +165,11 @@ hipError_t launch_multi(const PairArrays &a, int64_t n_pairs, const LaunchCfg &c
                         const PlanScratch &s, hipStream_t stream);
 hipError_t launch_antidiag(const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
                            const PlanScratch &s, hipStream_t stream);
+// Multi-stripe route on workgroups of `waves` waves (2, 4 or 8) sharing each
+// pair, stripes pipelined (dtw_pipe.hip).
+hipError_t launch_pipe(int waves, const PairArrays &a, int64_t n_pairs, const LaunchCfg &cfg,
+                       const PlanScratch &s, hipStream_t stream);
+int pipe_blocks_per_cu(int waves, bool extend);
 hipError_t launch_bnb(const BnbArgs &b, int grid, float *edge, hipStream_t stream);
 int bnb_blocks_per_cu();
 // per_candidate: n_events holds one count per candidate (anchored chains)

