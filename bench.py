@@ -498,6 +498,46 @@ def banded_leg(lib, valu_peak: float, opts=None, steps: int = 5, warmup: int = 1
             "entry_point": "rawalign_dtw_band", "workload": "chained_segments_100000"}
 
 
+def banded_regions_leg(lib, db, full_ms: float, steps: int = 3):
+    """Banded DTW of the uneven batch's candidate regions (1.2 to 3 times
+    the read) at a band of 20% of the region: time per batch against the
+    full table's, and the cells inside the band."""
+    import torch
+    b = db.batch
+    band = np.ceil(0.2 * b.r_len).astype(np.int32)
+    dband = torch.from_numpy(band).to(db.q.device)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        lib.rawalign_dtw_band(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, dband, db.score, db.end,
+                              stream=stream)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    end = db.end.cpu().numpy()
+    n = b.q_len.astype(np.int64)
+    m = b.r_len.astype(np.int64)
+    w = np.minimum(band.astype(np.int64), m - 1)
+    band_cells = 0
+    for lo in range(0, b.n_pairs, 5000):
+        nn, mm, ww = n[lo:lo + 5000], m[lo:lo + 5000], w[lo:lo + 5000]
+        rows = np.repeat(np.arange(len(nn)), nn)
+        i = np.arange(int(nn.sum())) - np.repeat(np.cumsum(nn) - nn, nn)
+        c = i * mm[rows] // nn[rows]
+        band_cells += int(np.maximum(np.minimum(c + ww[rows], mm[rows] - 1) - np.maximum(c - ww[rows], 0) + 1,
+                                     0).sum())
+    return {"ms_per_batch": ms, "full_table_ms": full_ms, "speedup_over_full_table": full_ms / ms,
+            "band_cells": band_cells, "full_table_cells": b.cells, "band_gcups": band_cells / (ms / 1e3) / 1e9,
+            "unsupported_pairs": int((end == -4).sum()), "pairs": b.n_pairs,
+            "entry_point": "rawalign_dtw_band", "workload": "uneven_batch_100000_pairs, band 20% of the region"}
+
+
 def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
     """Anchor-guided alignment (Sec. 2.4.2) of 100,000 candidate chains of
     reads shaped like the uneven batch: global DTW of every gap between
@@ -748,6 +788,7 @@ def main():
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
         variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
         variants["path"] = path_leg(lib, b, lib.make_opts(**extra))
+        variants["banded_regions"] = banded_regions_leg(lib, db, step_s * 1e3)
     if not args.skip_anchored:
         variants["anchored"] = anchored_leg(lib, valu_peak)
     if not args.skip_plain:

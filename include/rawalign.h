@@ -147,7 +147,7 @@ int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, 
  * and sentinels as rawalign_dtw_batch / rawalign_dtw_batch_ex with default
  * options (persistent queues, striped kernels, every kernel on `stream`),
  * but the planning lists and the multi-stripe kernel's edge slots live in
- * one fixed device array of RAWALIGN_NOALLOC_SCRATCH_BYTES (33.5 MiB) per
+ * one fixed device array of RAWALIGN_NOALLOC_SCRATCH_BYTES (34 MiB) per
  * GPU, which the library holds from its first use on that GPU until the
  * process ends.  The call makes no hipMalloc, hipFree or other allocating
  * call; the address of the array on the current device is looked up once
@@ -164,7 +164,7 @@ int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, 
  */
 #define RAWALIGN_NOALLOC_MAX_PAIRS 131072
 #define RAWALIGN_NOALLOC_EDGE_SLOTS 512
-#define RAWALIGN_NOALLOC_SCRATCH_BYTES 35129856
+#define RAWALIGN_NOALLOC_SCRATCH_BYTES 35654912
 int rawalign_dtw_batch_noalloc(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                                const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,
                                int64_t n_pairs, float *out_score, int32_t *out_end, void *stream);
@@ -335,15 +335,18 @@ int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, cons
  *   One wave per pair in a band-relative frame (frame positions follow the
  *   diagonal) when m <= n (at least as many events as levels, as in a
  *   chained segment: about 3.3 events per level) and 2*min(band, m-1)+1 <=
- *   2048; other pairs of at most 2048 levels use a frame over the whole
- *   region with the cells outside the band forced to +inf.  The pairs are
- *   planned on the device into three classes (band frames up to 512
- *   columns, wider band frames, whole-region frames), each taken longest
- *   first from a persistent queue; the class kernels run concurrently on
- *   internal streams joined back to `stream`.  Scratch: that of
- *   rawalign_dtw_batch, per (device, stream).
- *   Pairs of more than 2048 levels with m > n or a band wider than 2048
- *   columns get the sentinel NaN, end -4.  A negative band or an invalid
+ *   2048.  Other pairs use frames over the whole region with the cells
+ *   outside the band forced to +inf: one stripe up to 2048 levels, else
+ *   stripes of up to 2048 columns swept one after another, each over only
+ *   the rows the band spends in it.  The pairs are planned on the device
+ *   into four classes (band frames up to 512 columns, wider band frames,
+ *   one whole-region stripe, several stripes), each taken longest first
+ *   from a persistent queue; the class kernels run concurrently on internal
+ *   streams joined back to `stream`.  Scratch: that of rawalign_dtw_batch
+ *   plus stripe edge slots, per (device, stream).
+ *   A query longer than RAWALIGN_MAX_QUERY_LONG against more than 2048
+ *   levels with a band wider than 2048 columns (the one shape no class
+ *   takes) gets the sentinel NaN, end -4.  A negative band or an invalid
  *   slice gives NaN, -2; n == 0 gives (0, -1), m == 0 (+inf, -1).
  */
 int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,

@@ -376,6 +376,165 @@ void k_band_abs(PairArrays a, const int32_t *__restrict__ band, const int32_t *_
     }
 }
 
+// Class 3: regions above 2048 levels that the band-relative frame does not
+// take (more levels than events, or a band wider than 2048 columns).  One
+// wave sweeps the region stripe by stripe with the multi-stripe kernel's
+// shape (S = ceil(m / 2048) stripes of 64 C columns) and, as in class 2,
+// forces every cell outside its row's band to +inf.  A stripe over columns
+// [a, b] sweeps only the rows whose band meets it: [i0, i1] with i0 the
+// first row with c(i) >= a - w and i1 the last with c(i) <= b + w.  Its
+// rows before i0 are out of band (+inf; row -1 is the free start, zero),
+// and its rows after i1 reach neither row n-1 nor the next stripe, whose
+// west column reads +inf outside [i0, i1].  Lane 63 stores the stripe's
+// last column of rows [i0, i1] into the wave's edge slot, in place (a row
+// is read by a stripe before that stripe rewrites it).
+template <int C>
+RA_DEV void band_multi_stripe(const BandView &bv, int s, int a, int i0, int i1, int p0, int p1, float *edge,
+                              float &best, int &bj) {
+    const int lane = opaque_lane();
+    const int n = bv.n, m = bv.m, w = bv.w;
+    const int col0 = a + lane * C;
+    const __amdgpu_buffer_rsrc_t rrs = make_rsrc(bv.r, m);
+    const __amdgpu_buffer_rsrc_t qrs = make_rsrc(bv.q, n);
+    const __amdgpu_buffer_rsrc_t ers = make_rsrc(edge, n);
+    const int nm1 = n - 1;
+    float rv[C], A[C];
+    const float row_before = i0 == 0 ? 0.0f : kInf;   // row i0 - 1 in this stripe
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+        const int j = col0 + v;
+        const float lv = bload(rrs, j < m ? j : m - 1);
+        rv[v] = j < m ? lv : kInf;
+        A[v] = row_before;
+    }
+    // West value of row `row` for lane 0: the previous stripe's last column
+    // inside its rows [p0, p1], else +inf (out of band), row -1 zero.
+    auto west = [&](int row) -> float {
+        const float e = uload(ers, row < 0 ? 0 : row, nm1);
+        if (s == 0) return kInf;
+        return (row >= p0 && row <= p1) ? e : (row == -1 ? 0.0f : kInf);
+    };
+    // c(i) = floor(i*m/n) of this lane's row, from row i0 on.
+    const int64_t im = (int64_t)i0 * m;
+    int c = (int)(im / n), rem = (int)(im % n);
+    const int qd = m / n, rd = m % n;
+    const int ns = i1 - i0 + 1;
+    float ecur = west(i0 - 1), eprev, qv = 0.0f;
+    float qa = uload(qrs, i0, nm1), qb = uload(qrs, i0 + 1, nm1);
+    float ea = west(i0), eb = west(i0 + 1);
+    const int T = ns + 63;
+    for (int t = 0; t < T; ++t) {
+        const float q0 = qa, e0 = ea;
+        qa = qb;
+        qb = uload(qrs, i0 + t + 2, nm1);
+        ea = eb;
+        eb = west(i0 + t + 2);
+        qv = dpp_shr1(q0, qv);
+        eprev = ecur;
+        ecur = dpp_shr1(e0, A[C - 1]);
+        const bool valid = (unsigned)(t - lane) < (unsigned)ns;
+        const int lo = c - w - col0;   // band of this lane's row in lane positions: [lo, lo + 2w]
+        float diag = eprev, left = ecur;
+#pragma unroll
+        for (int v = 0; v < C; ++v) {
+            const float up = A[v];
+            float nv = fabsf(qv - rv[v]) + fminf(fminf(diag, up), left);
+            nv = (unsigned)(v - lo) <= (unsigned)(2 * w) ? nv : kInf;
+            diag = up;
+            left = nv;
+            A[v] = valid ? nv : A[v];
+        }
+        if (lane == 63 && valid) edge[i0 + t - 63] = A[C - 1];
+        if (valid) {
+            rem += rd;
+            const int carry = rem >= n ? 1 : 0;
+            rem -= carry ? n : 0;
+            c += qd + carry;
+        }
+    }
+    best = kInf;
+    bj = 0x7fffffff;
+    if (i1 == n - 1) {
+#pragma unroll
+        for (int v = 0; v < C; ++v)
+            if (col0 + v < m) take_min(best, bj, A[v], col0 + v);
+    }
+    wave_min(best, bj);
+}
+
+// First row whose diagonal column reaches X, last row whose diagonal column
+// is at most Y (c(i) = floor(i*m/n) is non-decreasing).
+RA_DEV int first_row_at(int64_t X, int n, int m) { return X <= 0 ? 0 : (int)((X * n + m - 1) / m); }
+RA_DEV int last_row_at(int64_t Y, int n, int m) { return Y < 0 ? -1 : (int)(((Y + 1) * n + m - 1) / m) - 1; }
+
+template <int C>
+RA_DEV void band_multi_pair(const BandView &bv, int S, float *edge, float &best, int &bj) {
+    best = kInf;
+    bj = 0x7fffffff;
+    int p0 = 1, p1 = 0;   // the previous stripe's rows (none yet)
+    for (int s = 0; s < S; ++s) {
+        const int a = s * 64 * C;
+        const int b = (a + 64 * C < bv.m ? a + 64 * C : bv.m) - 1;
+        int i0 = first_row_at((int64_t)a - bv.w, bv.n, bv.m);
+        int i1 = last_row_at((int64_t)b + bv.w, bv.n, bv.m);
+        i1 = i1 < bv.n - 1 ? i1 : bv.n - 1;
+        if (i0 > i1) {   // the band does not meet this stripe
+            p0 = 1;
+            p1 = 0;
+            continue;
+        }
+        float sb;
+        int sj;
+        band_multi_stripe<C>(bv, s, a, i0, i1, p0, p1, edge, sb, sj);
+        take_min(best, bj, sb, sj);
+        p0 = i0;
+        p1 = i1;
+        // Lane 63's edge stores must be visible to lane 0 of the next stripe.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    if (!(best < kInf)) bj = -1;
+}
+
+template <int H>
+RA_DEV void band_multi_dispatch(int h, const BandView &bv, int S, float *edge, float &best, int &bj) {
+    if constexpr (H <= kMultiMaxH) {
+        if (h == H)
+            band_multi_pair<kMultiColStep * H>(bv, S, edge, best, bj);
+        else
+            band_multi_dispatch<H + 1>(h, bv, S, edge, best, bj);
+    }
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_band_multi(PairArrays a, const int32_t *__restrict__ band, const int32_t *__restrict__ list,
+                  const int32_t *__restrict__ count, int32_t *queue, float *edge_base) {
+    float *edge = edge_base + (size_t)blockIdx.x * kEdgeCap;
+    const int n_items = *count;
+    int it = 0;
+    if (__lane_id() == 0) it = atomicAdd(queue, 1);
+    int item = __builtin_amdgcn_readfirstlane(it);
+    while (item < n_items) {
+        const int p = list[item];
+        const int n = a.q_len[p];
+        const int m = a.r_len[p];
+        const int wraw = band[p];
+        const int w = wraw < m - 1 ? wraw : m - 1;
+        const BandView bv{a.q + a.q_off[p], a.r + a.r_off[p], n, m, w, 2 * w + 1};
+        int S, h;
+        stripe_shape(m, S, h, false);
+        float best = __builtin_nanf("");
+        int bj = -2;
+        band_multi_dispatch<kMultiMinH>(h, bv, S, edge, best, bj);
+        if (__lane_id() == 0) {
+            a.out_score[p] = best;
+            a.out_end[p] = bj;
+        }
+        if (__lane_id() == 0) it = atomicAdd(queue, 1);
+        item = __builtin_amdgcn_readfirstlane(it);
+    }
+}
+
 // Class 0 (C <= 8) fits 64 VGPRs: eight waves per SIMD; class 1 four.
 #define RA_BAND_LO k_band<1, kBandLoMaxH, 8>
 #define RA_BAND_HI k_band<kBandLoMaxH + 1, kBandMaxFrame / 128, 4>
@@ -389,8 +548,11 @@ hipError_t launch_band(int cls, const PairArrays &a, const int32_t *band, int gr
         hipLaunchKernelGGL(RA_BAND_LO, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
     else if (cls == 1)
         hipLaunchKernelGGL(RA_BAND_HI, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
-    else
+    else if (cls == 2)
         hipLaunchKernelGGL(k_band_abs, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue);
+    else   // one edge slot per workgroup: grid <= the slots
+        hipLaunchKernelGGL(k_band_multi, dim3((unsigned)grid), dim3(64), 0, stream, a, band, list, count, queue,
+                           s.edge);
     return hipGetLastError();
 }
 
@@ -400,8 +562,10 @@ int band_blocks_per_cu(int cls) {
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_LO, 64, 0);
     else if (cls == 1)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, RA_BAND_HI, 64, 0);
-    else
+    else if (cls == 2)
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_band_abs, 64, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_band_multi, 64, 0);
     return nb > 0 ? nb : 1;
 }
 

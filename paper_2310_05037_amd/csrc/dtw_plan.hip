@@ -16,11 +16,14 @@ struct PlanArgs {
 
 // Banded pairs (dtw_band.hip): class 0 for frames of at most kBandLoMaxH*128
 // columns, class 1 for wider ones, longest first by the frame cells swept;
-// class 2 for the shapes the band-relative frame does not take (more levels
-// than events, or a band wider than one wave's frame) when the whole region
-// fits one wave's frame.  Pairs that need no kernel get their result here:
-// NaN/-2 for an invalid slice or a negative band, (0, -1) for an empty
-// query, (+inf, -1) for an empty region, NaN/-4 for the remaining shapes.
+// for the shapes the band-relative frame does not take (more levels than
+// events, or a band wider than one wave's frame), class 2 when the whole
+// region fits one wave's frame and class 3 (stripes) above that.  Pairs
+// that need no kernel get their result here: NaN/-2 for an invalid slice
+// or a negative band, (0, -1) for an empty query, (+inf, -1) for an empty
+// region, NaN/-4 for the one shape left: a query longer than a stripe edge
+// column (kEdgeCap) against more than 2048 levels with a band wider than
+// 2048 columns.
 RA_DEV int band_classify(const PlanArgs &pa, int64_t p, int &bucket, float &score, int &end) {
     const PairArrays &a = pa.a;
     const int n = a.q_len[p];
@@ -45,6 +48,18 @@ RA_DEV int band_classify(const PlanArgs &pa, int64_t p, int &bucket, float &scor
             b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
             bucket = kBuckets - 1 - b;
             return 2;
+        }
+        if (n <= kEdgeCap) {
+            // stripes of the band's rows only: about the rows the band
+            // spends in each stripe times its width
+            int S, h;
+            const int cols = stripe_shape(m, S, h, false);
+            const float rows = fminf((float)n, (float)(cols + W) * (float)n / (float)m + 64.0f);
+            const float work = rows * (float)(S * cols) + 1.0f;
+            int b = (int)(4.0f * __log2f(work));
+            b = b < 0 ? 0 : (b >= kBuckets ? kBuckets - 1 : b);
+            bucket = kBuckets - 1 - b;
+            return 3;
         }
         score = __builtin_nanf("");
         end = -4;

@@ -15,7 +15,11 @@ namespace ra {
 //   single_hi: one stripe, 34..64 columns per lane (region <= 4096 levels)
 //   multi:     several stripes of at most 256 kMultiMaxK columns swept one
 //              after another by the same wave (region > 4096 levels)
-enum Route : int { kRouteSingleLo = 0, kRouteSingleHi = 1, kRouteMulti = 2, kNumRoutes = 3 };
+// The banded planner (dtw_plan.hip, band mode) uses the same lists for its
+// four pair classes, so there are four lists although plain batches use
+// three.
+enum Route : int { kRouteSingleLo = 0, kRouteSingleHi = 1, kRouteMulti = 2, kNumRoutes = 4 };
+constexpr int kNumBandClasses = 4;
 
 constexpr int kMaxColsPerLane = 64;
 constexpr int kShortMaxRegion = 64 * kMaxColsPerLane;  // 4096: the widest single stripe

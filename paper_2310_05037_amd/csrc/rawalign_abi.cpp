@@ -815,8 +815,10 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
     DeviceInfo info;
     rc = device_info(dev, info);
     if (rc) return rc;
+    // Class 3 (striped band frames) gives each resident wave an edge slot.
+    const int grid3 = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(3), n_pairs);
     StreamScratch *s = nullptr;
-    rc = get_scratch(dev, c.stream, n_pairs, 0, 0, false, true, s);
+    rc = get_scratch(dev, c.stream, n_pairs, grid3, 0, false, true, s);
     if (rc) return rc;
     ra::PairArrays a;
     a.q = q;
@@ -838,17 +840,20 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
     const ra::PlanScratch ps = plan_view(*s);
     hipError_t e = ra::launch_band_plan(a, band, n_pairs, ps, c.stream);
     if (e != hipSuccess) return hip_fail(e, "banded planning");
-    // The band classes run concurrently on internal streams joined back to
-    // the caller's stream.
+    // The band classes run concurrently on the three internal streams (the
+    // two whole-region classes share one) joined back to the caller's stream.
     if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    for (int cls = 0; cls < 3; ++cls) {
-        if ((e = hipStreamWaitEvent(s->sub[cls], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-        const int grid = (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(cls), n_pairs);
-        e = ra::launch_band(cls, a, band, grid, ps, s->sub[cls]);
+    for (int i = 0; i < 3; ++i)
+        if ((e = hipStreamWaitEvent(s->sub[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    for (int cls = 0; cls < ra::kNumBandClasses; ++cls) {
+        const int grid = cls == 3 ? grid3
+                                  : (int)std::min<int64_t>((int64_t)info.cus * ra::band_blocks_per_cu(cls), n_pairs);
+        e = ra::launch_band(cls, a, band, grid, ps, s->sub[cls < 3 ? cls : 2]);
         if (e != hipSuccess) return hip_fail(e, "banded kernel");
-        if ((e = hipEventRecord(s->join[cls], s->sub[cls])) != hipSuccess) return hip_fail(e, "hipEventRecord");
-        if ((e = hipStreamWaitEvent(c.stream, s->join[cls], 0)) != hipSuccess)
-            return hip_fail(e, "hipStreamWaitEvent");
+    }
+    for (int i = 0; i < 3; ++i) {
+        if ((e = hipEventRecord(s->join[i], s->sub[i])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipStreamWaitEvent(c.stream, s->join[i], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     return RAWALIGN_OK;
 }

@@ -108,24 +108,68 @@ def test_band_exact_on_dyadic_inputs(L):
 
 
 def test_band_sentinels(L):
-    """More than 2048 levels with a band frame wider than 2048 columns (or
-    m > n): NaN, -4; a negative band or an invalid slice: NaN, -2; empty
-    query (0, -1); empty region (+inf, -1).  m > n in a short region goes
-    to the whole-region kernel and matches the oracle."""
+    """The one unsupported shape (a query longer than a stripe edge column
+    against more than 2048 levels with a band wider than 2048 columns):
+    NaN, -4; a negative band or an invalid slice: NaN, -2; empty query
+    (0, -1); empty region (+inf, -1).  A band wider than 2048 columns over
+    more than 2048 levels with a shorter query takes the striped band
+    frames and matches the oracle, as does m > n in a short region."""
     rng = np.random.default_rng(11)
-    ns = [50, 3000, 20, 0, 10, 40, 40]
-    ms = [80, 2500, 10, 5, 0, 30, 30]
+    ns = [50, 3000, 20, 0, 10, 40, 40, L.RAWALIGN_MAX_QUERY_LONG + 100]
+    ms = [80, 2500, 10, 5, 0, 30, 30, 3000]
     b = _pairs(rng, ns, ms, "band_sentinels")
-    band = np.array([5, 1100, -1, 3, 3, 4, 4], np.int32)
+    band = np.array([5, 1100, -1, 3, 3, 4, 4, 1100], np.int32)
     q_off = b.q_off.copy()
     q_off[6] = len(b.q)           # slice past the end of q
     b = W.Batch(b.name, b.q, b.r, q_off, b.q_len, b.r_off, b.r_len, b.cand_off, b.cand_cnt, b.n_events,
                 b.true_pair, b.meta)
     s, e = _gpu_band(L, b, band)
-    assert e[0] >= 0 and math.isnan(s[1]) and e[1] == -4
+    assert e[0] >= 0 and e[1] >= 0 and math.isnan(s[7]) and e[7] == -4
     assert math.isnan(s[2]) and e[2] == -2 and math.isnan(s[6]) and e[6] == -2
     assert s[3] == 0.0 and e[3] == -1 and s[4] == np.inf and e[4] == -1
-    _check(b, band, s, e, np.array([0, 5]))
+    _check(b, band, s, e, np.array([0, 1, 5]))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_band_striped_frames_every_shape(L, seed):
+    """Regions above 2048 levels that the band-relative frame does not take
+    (the striped band frames): 1.2 to 4 levels per event, and bands wider
+    than 2048 columns with at most one level per event; half-widths from 0
+    (no path for a steep band) to past the table; stripes the band misses;
+    one to 20 stripes.  Scores and ends bit for bit against the float
+    oracle."""
+    rng = np.random.default_rng(900 + seed)
+    ns, ms, ws = [], [], []
+    for m in [2049, 2500, 4096, 4097, 6000, 8191, 12000, 20000, 40000]:
+        for ratio in (1.2, 2.0, 4.0):
+            n = max(1, int(m / ratio) // (8 if m > 8000 else 1))
+            for w in (0, int(rng.integers(1, 64)), int(0.2 * m), int(rng.integers(0, m + 1)), m + 3):
+                ns.append(n), ms.append(m), ws.append(w)
+    for m in (2100, 3000, 5000):                 # m <= n with a band wider than 2048 columns
+        ns.append(m + 37), ms.append(m), ws.append(int(rng.integers(1025, m)))
+    b = _pairs(rng, ns, ms, f"band_striped_{seed}")
+    band = np.array(ws, np.int32)
+    s, e = _gpu_band(L, b, band)
+    assert (e >= -1).all() and (e >= 0).sum() > len(ns) // 2
+    _check(b, band, s, e)
+
+
+def test_band_uneven_batch_20pct(L):
+    """The 100,000-pair uneven batch (candidate regions of 1.2 to 3 times
+    the read) at a band of 20% of the region: no unsupported pair, and a
+    sample stratified by region length and band width matches the float
+    oracle bit for bit."""
+    b = W.uneven_batch()
+    band = np.ceil(0.2 * b.r_len).astype(np.int32)
+    s, e = _gpu_band(L, b, band)
+    assert not (e == -4).any() and not (e == -2).any()
+    m = b.r_len.astype(np.int64)
+    rng = np.random.default_rng(77)
+    strata = np.digitize(m, [2048, 4096, 8192, 16384])
+    pick = [rng.choice(np.flatnonzero(strata == k), size=min(12, int((strata == k).sum())), replace=False)
+            for k in np.unique(strata)]
+    pick.append(np.array([int(np.argmax(b.q_len.astype(np.int64) * m))]))
+    _check(b, band, s, e, np.unique(np.concatenate(pick)))
 
 
 @pytest.mark.parametrize("seed", [0, 1])
@@ -165,7 +209,7 @@ def test_band_chained_segments_full_size_sampled(L):
     launch the benchmark times): on a sample stratified by frame width (every
     columns-per-lane class) plus random pairs, scores and ends bit for bit
     against the float oracle; the pairs with more levels than events are
-    checked too, and only unsupported shapes carry the -4 sentinel."""
+    checked too, and no pair carries the -4 sentinel."""
     ab = W.anchored_chains()
     b, band = W.chained_segments(ab)
     s, e = _gpu_band(L, b, band)
@@ -179,11 +223,10 @@ def test_band_chained_segments_full_size_sampled(L):
     pick.append(rng.choice(b.n_pairs, size=120, replace=False))
     pairs = np.unique(np.concatenate(pick))
     _check(b, band, s, e, pairs)
-    unsupported = (m > 2048) & ((m > n) | (2 * w + 1 > 2048))
-    assert np.array_equal(np.flatnonzero(e == -4), np.flatnonzero(unsupported))
+    assert not (e == -4).any()
     ok = e >= 0
-    assert ok.sum() == b.n_pairs - int(unsupported.sum())
-    more = np.flatnonzero((m > n) & ~unsupported)
+    assert ok.sum() == b.n_pairs
+    more = np.flatnonzero(m > n)
     if len(more):
         _check(b, band, s, e, more)
     assert np.all(np.isfinite(s[ok]))
