@@ -1,169 +1,300 @@
-// dtw_antidiag.hip -- regions longer than 4096 levels in anti-diagonal order.
+// dtw_antidiag.hip -- regions above one stripe in anti-diagonal order.
 //
 // The paper vectorises its DTW by walking the table anti-diagonal by
 // anti-diagonal (Sec. 2.4.4): the cells of one anti-diagonal depend only on
 // the two before it, so they can all be computed at once.  This kernel is
-// that scheme on one workgroup per pair, kept as the comparison variant of
-// the lane-striped kernel (RAWALIGN_LONG_ANTIDIAG):
-//   * the query rows are taken in blocks of 256 R (R = 1, 2 or 4 by query
-//     length); thread t owns the R consecutive rows i0 + R t .. + R-1, and at
-//     step e of the block it computes their cells on anti-diagonal
-//     e = (i - i0) + j, so every step is one anti-diagonal of the block;
-//   * inside a thread the north, west and north-west neighbours and the
-//     levels come from registers (a row's level at step e is the level the
-//     row above used at step e-1); only the block-internal boundary crosses
-//     threads: thread t writes its last row's value to LDS and thread t+1
-//     reads it one step later as the north neighbour of its first row;
-//   * the row above the block, D(i0-1, .), comes from the workgroup's row
-//     buffer in device memory: the previous block's last row writes it in
-//     place as it goes (column j is staged for the new block's first row
-//     before its last row rewrites it, at step j + h - 1 >= j); the first
-//     block uses row -1 = 0 instead;
-//   * the levels and the row above are staged through LDS rings of three
-//     chunks of 256 R columns, each loaded one chunk (256 R steps) ahead;
-//   * one LDS-only workgroup barrier per step separates the LDS writes of
-//     step e from the reads of step e+1 (and the reads of e from the writes
-//     of e+1, which reuse the buffer of e-1); a full barrier between blocks
-//     makes the row buffer's stores visible.
-// Every thread runs the same block and step loops with the same bounds, so
-// every thread reaches every barrier.  The thread holding row n-1 tracks the
-// running minimum of the last row as the steps pass it (columns increase
-// with e, so a strict < keeps the smallest column on ties).
+// that scheme on one workgroup of 256 threads per pair, kept as the
+// comparison variant of the lane-striped kernel (RAWALIGN_LONG_ANTIDIAG),
+// with the unit of the wavefront widened from one cell to a tile:
+//   * the query rows are taken in blocks of 256 R (R = 2, 4 or 8, chosen per
+//     pair from a cost model); thread t owns rows R t .. R t + R-1 of every
+//     block, and the region's columns are cut into tiles of K = 8;
+//   * tiles are numbered in one stream g = rb S + b over (row block rb,
+//     column tile b), with a row-block stride S >= the tile count (the tiles
+//     b in [tiles, S) are idle).  At step E thread t computes its R x K tile
+//     g = E - t, so one step is one anti-diagonal of tiles, and thread 0
+//     starts row block rb+1 while the later threads are still in rb: there
+//     is no fill or drain between row blocks;
+//   * inside a tile the north, west and north-west neighbours come from
+//     registers; only tile edges cross threads: thread t writes the K values
+//     of its last row to LDS and thread t+1 reads them at the next step as
+//     the row above its first row (double-buffered by step parity, one LDS
+//     barrier per step);
+//   * thread 0's row above is the last row of the previous row block, which
+//     thread 255 stores into the workgroup's row buffer in device memory S -
+//     255 steps before thread 0 needs it; the stride S >= 255 + 4 chunk
+//     lengths keeps that store at least one chunk ahead of the staging load
+//     that reads it (the first row block uses row -1 = 0);
+//   * the levels and thread 0's row above are staged through LDS rings in
+//     chunks of 32 tiles (one float per thread), written two chunks ahead of
+//     their first use from registers loaded one chunk before that;
+//   * rings and edge buffers are split into two halves of four floats per
+//     tile, so the 16-byte reads and writes of neighbouring threads fall on
+//     consecutive banks.
+// Every thread runs the same step loop with the same bounds, so every thread
+// reaches every barrier.  Tiles past the query (rows >= n) are computed and
+// discarded.  The thread holding row n-1 tracks the running minimum of the
+// last row (columns increase along its tiles, so a strict < keeps the
+// smallest column on ties).
 #include "dtw_device.h"
 
 namespace ra {
 
 constexpr int kAdThreads = 256;
+constexpr int kAdK = 8;                                      // columns per tile
+constexpr int kAdMaxR = 8;                                   // rows per thread, at most
+constexpr int kAdChunk = kAdThreads / kAdK;                  // tiles per staged chunk (32)
+constexpr int kAdLvChunks = 16;                              // level ring: >= 256 / 32 + 2 chunks live
+constexpr int kAdUpChunks = 4;                               // row-above ring: >= 3 chunks live
+constexpr int kAdLvHalf = 4 * kAdChunk * kAdLvChunks;        // floats per half of the level ring
+constexpr int kAdUpHalf = 4 * kAdChunk * kAdUpChunks;
+constexpr int kAdMinStride = kAdThreads + 4 * kAdChunk;      // 384 tiles
+constexpr int kAdStepCost = 24;                              // per-step overhead in VALU slots (cost model)
+
+// LDS layout, in floats.  Every 8-value access (a tile's levels, a row
+// segment) is two 16-byte halves at the same offset in half 0 and half 1,
+// kAdHalf apart:
+//   lv   [kAdLvHalf]   levels of tile g at (4 g) mod kAdLvHalf
+//   up   [kAdUpHalf]   thread 0's row above, same layout
+//   edge [4 x 256]     last row of thread t at 4 t (read by lane t+1 of the
+//                      same wave; single-buffered: within a wave the read of
+//                      step E+1 follows the write of step E in program order)
+//   bnd  [2 x 4 x 4]   last row of lane 63 of wave w at step parity p, for
+//                      lane 0 of wave w+1 (double-buffered across the barrier)
+// after both halves, the query rows: thread t's R rows at kAdQ + R t.
+constexpr int kAdLv = 0;
+constexpr int kAdUp = kAdLv + kAdLvHalf;
+constexpr int kAdEdge = kAdUp + kAdUpHalf;
+constexpr int kAdBnd = kAdEdge + 4 * kAdThreads;
+constexpr int kAdHalf = kAdBnd + 2 * 4 * 4;
+constexpr int kAdQ = 2 * kAdHalf;
+constexpr int kAdLds = kAdQ + kAdMaxR * kAdThreads;
 
 // Workgroup barrier that orders LDS accesses only: global loads issued
-// before it stay in flight (the prefetches below rely on that).
+// before it stay in flight (the staging loads rely on that).
 RA_DEV void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// LDS of one workgroup, sized for the largest R.
-constexpr int kAdMaxR = 4;
-constexpr int kAdRingMax = 3 * kAdThreads * kAdMaxR;
-struct AdShared {
-    float edge[2][kAdThreads];     // last row of every thread at steps e-1 / e
-    float rring[kAdRingMax];       // levels, chunk k in slot k mod 3
-    float uring[kAdRingMax];       // row above the block, same layout
+// Per-pair shape of the tile stream (uniform across the workgroup).
+struct AdShape {
+    int R, W;        // rows per thread, rows per block (256 R)
+    int tiles;       // column tiles, ceil(m / K)
+    int stride;      // tiles per row block in the stream, max(tiles, kAdMinStride)
+    int blocks;      // row blocks, ceil(n / W)
+    int last_tile;   // stream index of the last tile with work
+    int t_l, s_l;    // thread and row slot of query row n-1
 };
 
-// Chunk k = columns [W k, W k + W), W = 256 R, sits in ring slot k mod 3.  At
-// step e thread t's first row reads column e - R t in [e - W + R, e], i.e.
-// chunks c-1 and c (c = e / W); chunk c+1 is written into the slot of chunk
-// c-2 at the last step of chunk c, from registers loaded W steps earlier.
+RA_DEV AdShape ad_shape(int n, int m, int R) {
+    AdShape a;
+    a.R = R;
+    a.W = kAdThreads * R;
+    a.tiles = (m + kAdK - 1) / kAdK;
+    a.stride = a.tiles > kAdMinStride ? a.tiles : kAdMinStride;
+    a.blocks = (n + a.W - 1) / a.W;
+    a.last_tile = (a.blocks - 1) * a.stride + a.tiles - 1;
+    const int rel = (n - 1) - (a.blocks - 1) * a.W;
+    a.t_l = rel / R;
+    a.s_l = rel % R;
+    return a;
+}
+
+// Steps a shape takes (the last tile reaches thread t_l), times the VALU
+// slots of one step.
+RA_DEV long long ad_cost(const AdShape &a) {
+    return (long long)(a.last_tile + a.t_l + 1) * (3 * a.R * kAdK + kAdStepCost);
+}
+
+// One element of a staged chunk: thread u holds column k = u % K of tile
+// g = 32 c + u / K.  Levels past the region and idle tiles stage 0; the row
+// above is 0 in the first row block (row -1) and read back from the row
+// buffer after it.
+struct AdStage {
+    float lv, up;
+};
+
+RA_DEV AdStage ad_stage_load(const PairView &pv, const float *prow, const AdShape &a, int chunk) {
+    const int u = threadIdx.x;
+    const int g = kAdChunk * chunk + u / kAdK;
+    const int rb = g / a.stride;
+    const int b = g - rb * a.stride;
+    const int col = kAdK * b + u % kAdK;
+    const bool in = b < a.tiles && col < pv.m;
+    AdStage s;
+    s.lv = in ? pv.r[col] : 0.0f;
+    s.up = (in && rb >= 1 && rb < a.blocks) ? prow[col] : 0.0f;
+    return s;
+}
+
+RA_DEV void ad_stage_store(float *f, const AdStage &s, int chunk) {
+    const int u = threadIdx.x;
+    const int g = kAdChunk * chunk + u / kAdK;
+    const int k = u % kAdK;
+    float *h = f + (k >> 2) * kAdHalf;
+    h[kAdLv + ((4 * g + (k & 3)) & (kAdLvHalf - 1))] = s.lv;
+    h[kAdUp + ((4 * g + (k & 3)) & (kAdUpHalf - 1))] = s.up;
+}
+
+// Eight values at LDS offset o (half 0) and o + kAdHalf (half 1).
+RA_DEV void ld8(const float *f, int o, float (&v)[kAdK]) {
+    const float4 a = *reinterpret_cast<const float4 *>(f + o);
+    const float4 b = *reinterpret_cast<const float4 *>(f + kAdHalf + o);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+RA_DEV void st8(float *f, int o, const float (&v)[kAdK]) {
+    *reinterpret_cast<float4 *>(f + o) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4 *>(f + kAdHalf + o) = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// Query rows R t .. R t + R-1 of row block `block` (0 past the query).
 template <int R>
-RA_DEV void antidiag_pair(const PairView &pv, float *prow, AdShared &sh, float &best, int &bj) {
-    constexpr int W = kAdThreads * R;
-    constexpr int RING = 3 * W;
+RA_DEV void ad_rows_load(const PairView &pv, const AdShape &a, int block, float (&q)[R]) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int i = block * a.W + R * (int)threadIdx.x + s;
+        q[s] = i < pv.n ? pv.q[i] : 0.0f;
+    }
+}
+
+template <int R>
+RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdShape &a, float &best, int &bj) {
+    constexpr int K = kAdK;
     const int t = threadIdx.x;
-    const int n = pv.n;
+    const int lane = t & 63;
+    const int wave = t >> 6;
     const int m = pv.m;
-    for (int i0 = 0; i0 < n; i0 += W) {
-        const int h = n - i0 < W ? n - i0 : W;   // rows in this block
-        const bool first_block = i0 == 0;
-        const bool last_block = i0 + h == n;
-        const int row0 = R * t;                  // first own row, relative to i0
-        // Full barrier: the previous block's row-buffer stores are visible
-        // and its last LDS reads are done.
-        __syncthreads();
-        float qv[R], prev[R], nw[R], rv[R];
+    float *qrow = f + kAdQ + R * t;   // this thread's query rows (private slot)
+    // Chunks 0 and 1 go straight to the rings; chunk 2 waits in registers.
+    ad_stage_store(f, ad_stage_load(pv, prow, a, 0), 0);
+    ad_stage_store(f, ad_stage_load(pv, prow, a, 1), 1);
+    AdStage staged = ad_stage_load(pv, prow, a, 2);
+    // Query rows: block 0 into the private slot now; block B >= 1 is loaded
+    // at the first chunk step after thread 255 has taken block B-1's rows
+    // and written one chunk step later, before thread 0 starts block B.
+    float qst[R];
+    ad_rows_load<R>(pv, a, 0, qst);
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-            qv[s] = row0 + s < h ? pv.q[i0 + row0 + s] : 0.0f;
-            prev[s] = kInf;   // D(i, -1) = +inf until the row's first cell
-            nw[s] = kInf;     // D(i-1, -1): +inf (row 0: row -1 is 0 anyway)
-            rv[s] = 0.0f;
-        }
-        float r_nx[R], u_nx[R];
+    for (int s = 0; s < R; ++s) qrow[s] = qst[s];
+    int q_next = 1;           // next row block whose rows are to be loaded
+    bool q_pending = false;   // qst holds rows not yet written to the slot
+    float qv[R], left[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            const int c0 = k * kAdThreads + t;          // chunk 0
-            const int c1 = W + c0;                      // chunk 1
-            sh.rring[c0] = c0 < m ? pv.r[c0] : 0.0f;
-            sh.uring[c0] = (!first_block && c0 < m) ? prow[c0] : 0.0f;
-            r_nx[k] = c1 < m ? pv.r[c1] : 0.0f;
-            u_nx[k] = (!first_block && c1 < m) ? prow[c1] : 0.0f;
-        }
-        lds_barrier();
-        const int n_steps = h + m - 1;
-        int ri = (RING - row0) % RING;   // ring index of column e - R t
-        int pos = 0;                     // e mod W
-        int slot = 1;                    // ring slot of chunk c+1
-        int jn = W;                      // first column of the chunk held in r_nx
-        for (int e = 0; e < n_steps; ++e) {
-            const float *prv = (e & 1) ? sh.edge[0] : sh.edge[1];   // step e-1
-            float *cur = (e & 1) ? sh.edge[1] : sh.edge[0];         // step e
-            const int j0 = e - row0;                                // column of the first own row
-            // Level of the first row from the ring; the others shift down.
+    for (int s = 0; s < R; ++s) {
+        qv[s] = 0.0f;
+        left[s] = kInf;
+    }
+    float upleft = kInf;
+    // Stream position of this thread's tile: g = E - t, b = column tile
+    // within row block rb (negative while the wavefront has not arrived).
+    int g = -t, rb = 0, b = -t;
+    const int E_end = a.last_tile + a.t_l;   // last step with work (thread t_l, last tile)
+    // LDS offsets of the edge read and write that do not depend on the step.
+    const int rd_edge = kAdEdge + 4 * (t - 1);
+    const int wr_edge = kAdEdge + 4 * t;
+    float lvn[K];
+    lds_barrier();
+    ld8(f, kAdLv + ((4 * g) & (kAdLvHalf - 1)), lvn);
+    for (int E = 0; E <= E_end; ++E) {
+        // Row above the first own row: the left neighbour's last row at
+        // step E-1 (lane t-1 of this wave, or lane 63 of the wave before
+        // through the boundary slot); for thread 0 the staged row above.
+        int rd = rd_edge;
+        if (lane == 0) rd = wave == 0 ? kAdUp + ((4 * E) & (kAdUpHalf - 1)) : kAdBnd + (((E - 1) & 1) * 4 + wave - 1) * 4;
+        float above[K];
+        ld8(f, rd, above);
+        const float up_last = above[K - 1];   // north-west of the next tile's first row
+        float lv[K];
 #pragma unroll
-            for (int s = R - 1; s > 0; --s) rv[s] = rv[s - 1];
-            rv[0] = sh.rring[ri];
-            // North neighbour of the first row: the row above the block, or
-            // the previous thread's last row at step e-1.
-            float up = t == 0 ? sh.uring[ri] : prv[t - 1];
+        for (int k = 0; k < K; ++k) lv[k] = lvn[k];
+        ld8(f, kAdLv + ((4 * (g + 1)) & (kAdLvHalf - 1)), lvn);
+        if (b == 0) {
+            // A new row block: column -1 is +inf, query rows of block rb.
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int j = j0 - s;
-                const bool act = row0 + s < h && j >= 0 && j < m;
-                const float v = cell(qv[s], rv[s], nw[s], up, prev[s]);
-                const float upn = prev[s];   // this row at step e-1: north of row s+1
-                if (act) {
-                    nw[s] = up;
-                    prev[s] = v;
-                }
-                up = upn;
+                left[s] = kInf;
+                qv[s] = qrow[s];
             }
-            // prev[] now holds step e for active rows.
-            cur[t] = prev[R - 1];
-            // The block's last row: row h-1 = R t_l + s_l.
+            upleft = kInf;
+        }
+        const bool live = g >= 0 && b < a.tiles && g <= a.last_tile;
+        if (live) {
+            const bool track = rb == a.blocks - 1 && t == a.t_l;
+            const int j0 = K * b;
+            float diag = upleft;
 #pragma unroll
             for (int s = 0; s < R; ++s) {
-                const int j = j0 - s;
-                if (row0 + s == h - 1 && j >= 0 && j < m) {
-                    if (last_block) {
-                        if (prev[s] < best) {
-                            best = prev[s];
-                            bj = j;
+                float w = left[s];
+                float d = diag;
+                diag = w;   // D(row, j0-1): the next row's north-west
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float n_ = above[k];
+                    const float v = cell(qv[s], lv[k], d, n_, w);
+                    d = n_;
+                    above[k] = v;
+                    w = v;
+                }
+                left[s] = w;
+                if (s == a.s_l && track) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        if (j0 + k < m && above[k] < best) {
+                            best = above[k];
+                            bj = j0 + k;
                         }
-                    } else {
-                        prow[j] = prev[s];   // row above the next block (column j was staged long ago)
                     }
                 }
             }
-            if (pos == W - 1) {
+            if (t == kAdThreads - 1 && rb < a.blocks - 1) {
+                // Last row of the block: the row above of block rb+1.
+                if (j0 + K <= m) {
+                    *reinterpret_cast<float4 *>(prow + j0) = make_float4(above[0], above[1], above[2], above[3]);
+                    *reinterpret_cast<float4 *>(prow + j0 + 4) = make_float4(above[4], above[5], above[6], above[7]);
+                } else {
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    sh.rring[slot * W + k * kAdThreads + t] = r_nx[k];
-                    sh.uring[slot * W + k * kAdThreads + t] = u_nx[k];
+                    for (int k = 0; k < K; ++k)
+                        if (j0 + k < m) prow[j0 + k] = above[k];
                 }
-                jn += W;
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int c = jn + k * kAdThreads + t;
-                    r_nx[k] = c < m ? pv.r[c] : 0.0f;
-                    u_nx[k] = (!first_block && c < m) ? prow[c] : 0.0f;
-                }
-                slot = slot == 2 ? 0 : slot + 1;
-                pos = 0;
-            } else {
-                ++pos;
             }
-            ri = ri == RING - 1 ? 0 : ri + 1;
-            lds_barrier();
         }
+        upleft = up_last;
+        st8(f, lane == 63 ? kAdBnd + ((E & 1) * 4 + wave) * 4 : wr_edge, above);
+        if ((E & (kAdChunk - 1)) == kAdChunk - 1) {
+            const int c = E / kAdChunk;
+            ad_stage_store(f, staged, c + 2);
+            staged = ad_stage_load(pv, prow, a, c + 3);
+            if (q_pending) {
+#pragma unroll
+                for (int s = 0; s < R; ++s) qrow[s] = qst[s];
+                q_pending = false;
+            }
+            if (q_next < a.blocks && E >= (q_next - 1) * a.stride + kAdThreads) {
+                ad_rows_load<R>(pv, a, q_next, qst);
+                q_pending = true;
+                ++q_next;
+            }
+        }
+        ++g;
+        ++b;
+        if (b == a.stride) {
+            b = 0;
+            ++rb;
+        }
+        lds_barrier();
     }
 }
 
 __global__ __launch_bounds__(kAdThreads) void k_antidiag(PairArrays a, const int32_t *__restrict__ list,
                                                          const int32_t *__restrict__ count, int32_t *queue,
                                                          float *rowbuf) {
-    __shared__ AdShared sh;
+    __shared__ float4 lds[kAdLds / 4];
     __shared__ int s_item;
+    float *f = reinterpret_cast<float *>(lds);
     float *prow = rowbuf + (size_t)blockIdx.x * kMaxRegion;
     const int n_items = *count;
     int item = blockIdx.x;
@@ -172,32 +303,33 @@ __global__ __launch_bounds__(kAdThreads) void k_antidiag(PairArrays a, const int
             if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
             __syncthreads();
             item = s_item;
-            __syncthreads();   // every thread has read s_item before it is written again
         }
+        // Every thread has read s_item (before thread 0 writes it again) and
+        // finished the previous pair's LDS reads (before the rings are
+        // rewritten).
+        __syncthreads();
         if (item >= n_items) break;   // uniform: item comes from LDS or blockIdx
         const int p = list[item];
         const PairView pv = pair_view<false>(a, p);
         float best = kInf;
         int bj = 0x7fffffff;
-        // The planner routes only pairs with 1 <= n <= kEdgeCap and
-        // 4096 < m <= kMaxRegion here.  Rows per thread by query length
-        // (uniform across the workgroup).
-        int R;
-        if (pv.n >= 2048)
-            R = 4;
-        else if (pv.n >= 512)
-            R = 2;
-        else
-            R = 1;
-        if (R == 4)
-            antidiag_pair<4>(pv, prow, sh, best, bj);
-        else if (R == 2)
-            antidiag_pair<2>(pv, prow, sh, best, bj);
-        else
-            antidiag_pair<1>(pv, prow, sh, best, bj);
-        // Row n-1 = i0 + R t + s of the last block.
-        const int last_rel = (pv.n - 1) % (kAdThreads * R);
-        if (threadIdx.x == last_rel / R) {
+        // The planner routes only pairs with 1 <= n <= kEdgeCap and regions
+        // above one stripe here.  Rows per thread: the cheapest of 2, 4, 8
+        // under the step-count model (uniform across the workgroup).
+        const AdShape a2 = ad_shape(pv.n, pv.m, 2), a4 = ad_shape(pv.n, pv.m, 4), a8 = ad_shape(pv.n, pv.m, 8);
+        const long long c2 = ad_cost(a2), c4 = ad_cost(a4), c8 = ad_cost(a8);
+        int tl;
+        if (c8 <= c4 && c8 <= c2) {
+            antidiag_pair<8>(pv, prow, f, a8, best, bj);
+            tl = a8.t_l;
+        } else if (c4 <= c2) {
+            antidiag_pair<4>(pv, prow, f, a4, best, bj);
+            tl = a4.t_l;
+        } else {
+            antidiag_pair<2>(pv, prow, f, a2, best, bj);
+            tl = a2.t_l;
+        }
+        if (threadIdx.x == tl) {
             a.out_score[p] = best;
             a.out_end[p] = bj;
         }

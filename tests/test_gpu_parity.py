@@ -147,9 +147,9 @@ def test_long_regions_multi_stripe(L):
 
 def test_antidiag_kernel_against_oracle(L):
     """The anti-diagonal kernel on its own: queries around its row-block
-    sizes (256 threads x 1, 2 or 4 rows, chosen at 512 and 2048 events) and
-    several blocks, regions just above one stripe up to the maximum, against
-    the float oracle bit for bit."""
+    sizes (256 threads x 2, 4 or 8 rows, picked per pair by a step-count
+    model) and several blocks, regions just above one stripe up to the
+    maximum, against the float oracle bit for bit."""
     from oracle import oracle
     rng = np.random.default_rng(5)
     ns = [1, 2, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 2048, 2049, 4096, 4097, 8193, 16384, 3, 700]
@@ -169,6 +169,49 @@ def test_antidiag_kernel_against_oracle(L):
         c32, e32 = oracle.dtw_f32(q, rr)
         assert s[p].view(np.uint32) == np.float32(c32).view(np.uint32) and e[p] == e32, p
     parity.check(b, s, e)
+
+
+def test_antidiag_short_regions_padded_stride(L):
+    """With the single-stripe cut-off at 2,048 levels the anti-diagonal
+    kernel takes regions of 2,049 levels up, whose 257..383 column tiles
+    are padded to a 384-tile row-block stride; queries span one to many
+    row blocks of every row count.  Equal to the oracle bit for bit and to
+    the lane-striped kernel, in persistent and plain mode."""
+    from oracle import oracle
+    rng = np.random.default_rng(6)
+    ns = [1, 5, 300, 511, 512, 513, 1100, 2049, 3000, 5000, 7, 640, 1537, 2048, 4097]
+    ms = [2049, 2050, 2100, 2500, 3071, 3072, 3073, 2049, 3200, 2300, 4096, 4095, 2056, 2400, 2049]
+    reads = [rng.standard_normal(n).astype(np.float32) for n in ns]
+    r = rng.standard_normal(sum(ms)).astype(np.float32)
+    pairs, off = [], 0
+    for i, m in enumerate(ms):
+        pairs.append((i, off, m, False))
+        off += m
+    b = W._pack("antidiag_short", reads, pairs, r, {})
+    s, e = _run(L, b, long_kernel=L.LONG_ANTIDIAG, single_max=2048)
+    for p in range(b.n_pairs):
+        q = b.q[b.q_off[p]:b.q_off[p] + b.q_len[p]]
+        rr = b.r[b.r_off[p]:b.r_off[p] + b.r_len[p]]
+        c32, e32 = oracle.dtw_f32(q, rr)
+        assert s[p].view(np.uint32) == np.float32(c32).view(np.uint32) and e[p] == e32, p
+    s2, e2 = _run(L, b, long_kernel=L.LONG_ANTIDIAG, single_max=2048, mode=L.MODE_PLAIN)
+    assert np.array_equal(s.view(np.uint32), s2.view(np.uint32)) and np.array_equal(e, e2)
+    s3, e3 = _run(L, b, single_max=2048)
+    assert np.array_equal(s.view(np.uint32), s3.view(np.uint32)) and np.array_equal(e, e3)
+
+
+def test_antidiag_uneven_batch(L):
+    """The 100,000-pair uneven batch with the anti-diagonal kernel on every
+    region above one stripe (at both cut-offs) equals the default path."""
+    b = W.uneven_batch()
+    db = L.DeviceBatch(b)
+    db.run(opts=L.make_opts())
+    ref = [x.copy() for x in db.results()]
+    for kw in (dict(long_kernel=L.LONG_ANTIDIAG), dict(long_kernel=L.LONG_ANTIDIAG, single_max=2048)):
+        print(f"  gpu: uneven batch {kw}", flush=True)
+        db.run(opts=L.make_opts(**kw))
+        s, e = db.results()
+        assert np.array_equal(s.view(np.uint32), ref[0].view(np.uint32)) and np.array_equal(e, ref[1]), kw
 
 
 def test_long_stress_antidiag_equals_striped(L):
