@@ -186,7 +186,8 @@ def valu_rate(iters: int = 20000):
     lane-operations per clock per CU for each form at 4 to 32 resident waves
     per CU, and the shader clock the cycle counter implies.  This is what
     the roofline's op peak (128 FP32 lane-operations per clock per CU, the
-    datasheet's 157.3 TFLOP/s without the FMA credit) rests on."""
+    datasheet's 157.3 TFLOP/s without the FMA credit) rests on; and the rate
+    of the constant clock behind the pipelined kernels' wait caps."""
     import ctypes
     import torch  # noqa: F401  (loads the HIP runtime first)
     path = os.path.join(ROOT, "paper_2310_05037_amd", "libvaluprobe.so")
@@ -207,6 +208,14 @@ def valu_rate(iters: int = 20000):
             row[f"{w}_waves_per_cu"] = {"lane_ops_per_clk_per_cu": rate.value, "clock_ghz": ghz.value,
                                         "kernel_ms": ms.value}
         out["forms"][name] = row
+    # Rate of the constant clock the pipelined kernels' capped waits count
+    # (s_memrealtime): ticks over one second of host wall time.
+    L.clock_probe.argtypes = [ctypes.c_int, ctypes.POINTER(d), ctypes.POINTER(d)]
+    ticks, secs = d(), d()
+    rc = L.clock_probe(1000, ctypes.byref(ticks), ctypes.byref(secs))
+    if rc != 0:
+        raise RuntimeError(f"clock_probe failed: {rc}")
+    out["memrealtime"] = {"ticks": ticks.value, "seconds": secs.value, "hz": ticks.value / secs.value}
     return out
 
 

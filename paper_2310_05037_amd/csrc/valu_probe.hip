@@ -15,6 +15,9 @@
 //   4  the DTW cell: v_sub_f32, v_min3_f32, v_add_f32 with an |x| source
 //      modifier (three instructions, three lane-operations per cell)
 #include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <thread>
 #include <stdint.h>
 
 namespace {
@@ -68,9 +71,48 @@ hipError_t launch(int blocks, int iters, float *sink, uint64_t *cycles) {
     return hipGetLastError();
 }
 
+// One thread reads the constant-rate clock that the pipelined kernels'
+// capped waits measure time with, and the shader cycle counter.
+__global__ void k_clock(uint64_t *out) {
+    if (threadIdx.x == 0) {
+        out[0] = __builtin_amdgcn_s_memrealtime();
+        out[1] = __builtin_amdgcn_s_memtime();
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Rate of s_memrealtime: two one-thread launches `sleep_ms` of host wall
+// time apart; *ticks receives the clock difference, *seconds the host time
+// between the two reads' completions.  Returns 0, -1 for a bad argument, -2
+// for a HIP error.
+int clock_probe(int sleep_ms, double *ticks, double *seconds) {
+    if (sleep_ms < 1 || sleep_ms > 10000) return -1;
+    uint64_t *d = nullptr;
+    if (hipMalloc(&d, 4 * sizeof(uint64_t)) != hipSuccess) return -2;
+    uint64_t h[4] = {0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    std::chrono::steady_clock::time_point t0, t1;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, 0, d + 2 * k);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (k == 0) {
+            t0 = std::chrono::steady_clock::now();
+            std::this_thread::sleep_for(std::chrono::milliseconds(sleep_ms));
+        } else {
+            t1 = std::chrono::steady_clock::now();
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return -2;
+    *ticks = (double)(h[2] - h[0]);
+    *seconds = std::chrono::duration<double>(t1 - t0).count();
+    return 0;
+}
 
 // Lane-operations per clock per CU of form `op` (see above) with
 // `waves_per_cu` single-wave workgroups on every CU, and the shader clock

@@ -117,3 +117,45 @@ def test_bnb_edge_cases(L):
         # pairs of reads 5 and 6 that both claim are never dropped
         shared = range(int(b.cand_off[6]), int(b.cand_off[5] + cc[5]))
         assert all(e[p] != -3 for p in shared)
+
+
+def _long_candidates(seed=7, n_reads=12, cands=5):
+    """Reads of 2,500-6,000 events, each with 5 candidate regions of
+    8,000-20,000 levels (4 to 10 stripes, over 2e7 cells per pair): the
+    true region at position k % cands of read k (first, middle, last),
+    read 0 all decoys."""
+    rng = np.random.default_rng(seed)
+    model = W.pore_model(rng)
+    bases = W.random_bases(rng, 2_000_000)
+    r = W.expected_levels(bases, model)
+    L = len(r)
+    reads, pairs = [], []
+    for k in range(n_reads):
+        n = int(rng.integers(2500, 6001))
+        start = int(rng.integers(0, L - 4 * n))
+        ev, span = W.read_events(rng, r, start, n_events=n)
+        reads.append(ev)
+        true_at = k % cands
+        for c in range(cands):
+            m = int(rng.integers(8000, 20001))
+            if c == true_at and k != 0:
+                pairs.append((k, W._true_region(rng, start, span, m, L), m, True))
+            else:
+                pairs.append((k, int(rng.integers(0, L - m + 1)), m, False))
+    return W._pack("long_candidates", reads, pairs, r, {})
+
+
+def test_bnb_long_candidates(L):
+    """Long candidates only (several stripes and many row blocks per pair,
+    true regions before, among and after decoys): decisions equal the
+    oracle's over full scores, completed pairs equal the float oracle bit
+    for bit, drops are justified, for two block sizes (one not dividing the
+    queries)."""
+    b = _long_candidates()
+    assert (b.r_len > 4096).all() and (b.q_len.astype(np.int64) * b.r_len >= 20_000_000).all()
+    s32, e32, _ = oracle.dtw_batch_f32(b.q, b.q_off, b.q_len, b.r, b.r_off, b.r_len, parity.threads())
+    for block_rows in (512, 200):
+        s, e, ob, os_, om = _run_bnb(L, b, block_rows=block_rows)
+        n_pruned = _check(b, s, e, ob, os_, om, s32, e32)
+        print("long", block_rows, "pruned", n_pruned, "of", b.n_pairs, "mapped", int(om.sum()))
+        assert n_pruned > 0 and not np.isnan(s).any()
