@@ -85,7 +85,7 @@ typedef struct rawalign_opts {
     int32_t long_kernel;        /* RAWALIGN_LONG_* */
     int32_t lo_waves_per_cu;    /* persistent grid of the <= 2048-level kernel, per CU (0 = occupancy limit) */
     int32_t hi_waves_per_cu;    /* same, 2049..4096 levels */
-    int32_t long_waves_per_cu;  /* same, > 4096 levels (anti-diagonal kernel: workgroups per CU, 0 = 4) */
+    int32_t long_waves_per_cu;  /* same, > 4096 levels (anti-diagonal kernel: workgroups per CU, 0 = occupancy, 5) */
     int32_t streams;            /* 1: the three kernels run one after another on `stream`;
                                    3: concurrently on internal streams joined back to `stream` */
     int32_t flags;              /* RAWALIGN_FLAG_* */

@@ -18,8 +18,10 @@
 //   * inside a tile the north, west and north-west neighbours come from
 //     registers; only tile edges cross threads: thread t writes the K values
 //     of its last row to LDS and thread t+1 reads them at the next step as
-//     the row above its first row (double-buffered by step parity, one LDS
-//     barrier per step);
+//     the row above its first row.  Within a wave one buffer suffices (the
+//     read of step E+1 follows the write of step E in program order); lane
+//     63 hands over to lane 0 of the next wave through a slot
+//     double-buffered by step parity.  One LDS barrier per step;
 //   * thread 0's row above is the last row of the previous row block, which
 //     thread 255 stores into the workgroup's row buffer in device memory S -
 //     255 steps before thread 0 needs it; the stride S >= 255 + 4 chunk
@@ -27,7 +29,9 @@
 //     that reads it (the first row block uses row -1 = 0);
 //   * the levels and thread 0's row above are staged through LDS rings in
 //     chunks of 32 tiles (one float per thread), written two chunks ahead of
-//     their first use from registers loaded one chunk before that;
+//     their first use from registers loaded one chunk before that; the query
+//     rows of a thread's next row block go to a private LDS slot at such a
+//     chunk step, so the step loop never waits for a global load;
 //   * rings and edge buffers are split into two halves of four floats per
 //     tile, so the 16-byte reads and writes of neighbouring threads fall on
 //     consecutive banks.
@@ -44,7 +48,7 @@ constexpr int kAdThreads = 256;
 constexpr int kAdK = 8;                                      // columns per tile
 constexpr int kAdMaxR = 8;                                   // rows per thread, at most
 constexpr int kAdChunk = kAdThreads / kAdK;                  // tiles per staged chunk (32)
-constexpr int kAdLvChunks = 16;                              // level ring: >= 256 / 32 + 2 chunks live
+constexpr int kAdLvChunks = 10;                              // level ring: 256 / 32 + 2 chunks live
 constexpr int kAdUpChunks = 4;                               // row-above ring: >= 3 chunks live
 constexpr int kAdLvHalf = 4 * kAdChunk * kAdLvChunks;        // floats per half of the level ring
 constexpr int kAdUpHalf = 4 * kAdChunk * kAdUpChunks;
@@ -134,7 +138,7 @@ RA_DEV void ad_stage_store(float *f, const AdStage &s, int chunk) {
     const int g = kAdChunk * chunk + u / kAdK;
     const int k = u % kAdK;
     float *h = f + (k >> 2) * kAdHalf;
-    h[kAdLv + ((4 * g + (k & 3)) & (kAdLvHalf - 1))] = s.lv;
+    h[kAdLv + (4 * g + (k & 3)) % kAdLvHalf] = s.lv;
     h[kAdUp + ((4 * g + (k & 3)) & (kAdUpHalf - 1))] = s.up;
 }
 
@@ -198,7 +202,10 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     const int wr_edge = kAdEdge + 4 * t;
     float lvn[K];
     lds_barrier();
-    ld8(f, kAdLv + ((4 * g) & (kAdLvHalf - 1)), lvn);
+    // Level-ring offset of the tile each step prefetches, tile g + 1 (kept
+    // in [0, kAdLvHalf) for the negative tiles of the wavefront's arrival).
+    int lvi = ((4 * (1 - t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf;
+    ld8(f, kAdLv + ((4 * (-t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf, lvn);
     for (int E = 0; E <= E_end; ++E) {
         // Row above the first own row: the left neighbour's last row at
         // step E-1 (lane t-1 of this wave, or lane 63 of the wave before
@@ -211,7 +218,8 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         float lv[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) lv[k] = lvn[k];
-        ld8(f, kAdLv + ((4 * (g + 1)) & (kAdLvHalf - 1)), lvn);
+        ld8(f, kAdLv + lvi, lvn);
+        lvi = lvi + 4 == kAdLvHalf ? 0 : lvi + 4;
         if (b == 0) {
             // A new row block: column -1 is +inf, query rows of block rb.
 #pragma unroll
@@ -289,7 +297,7 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     }
 }
 
-__global__ __launch_bounds__(kAdThreads) void k_antidiag(PairArrays a, const int32_t *__restrict__ list,
+__global__ __launch_bounds__(kAdThreads) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_antidiag(PairArrays a, const int32_t *__restrict__ list,
                                                          const int32_t *__restrict__ count, int32_t *queue,
                                                          float *rowbuf) {
     __shared__ float4 lds[kAdLds / 4];

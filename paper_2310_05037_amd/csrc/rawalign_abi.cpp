@@ -347,9 +347,10 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
     else
         cfg.multi_grid = grid_of(info.cus, o.long_waves_per_cu, ra::multi_blocks_per_cu(ext));
     // Anti-diagonal kernel: opts.long_waves_per_cu counts its workgroups per
-    // CU; by default at most 4, since each holds a 256 KiB row buffer.
+    // CU; by default its occupancy limit (5: LDS and registers), each with a
+    // 256 KiB row buffer.
     const int ad_occ = ra::antidiag_blocks_per_cu();
-    cfg.antidiag_grid = info.cus * std::min(o.long_waves_per_cu ? o.long_waves_per_cu : 4, ad_occ);
+    cfg.antidiag_grid = info.cus * (o.long_waves_per_cu ? std::min(o.long_waves_per_cu, ad_occ) : ad_occ);
     // A persistent grid never needs more workgroups than the batch has pairs
     // (a small batch would otherwise launch thousands of waves that only
     // start and exit).
