@@ -585,6 +585,11 @@ def anchored_leg(lib, valu_peak: float, steps: int = 10, warmup: int = 2):
             "workload": "anchored_chains_100000"}
 
 
+def note(msg: str):
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def timed_steps(lib, db, opts, steps: int, warmup: int):
     """Seconds per call of rawalign_dtw_batch_ex on a DeviceBatch and the mean
     per-kernel times (HIP events on the streams the kernels run on)."""
@@ -749,6 +754,7 @@ def main():
         # The library times its candidate launch settings on this batch and
         # keeps the fastest; the timed path uses it.
         t0 = time.perf_counter()
+        note("autotune on the uneven batch")
         best = lib.rawalign_autotune(*db.args())
         tune_ms = (time.perf_counter() - t0) * 1e3
         extra = {k: v for k, v in best.as_dict().items() if k != "flags"}
@@ -761,6 +767,7 @@ def main():
     def timed(opts, steps, warmup):
         return timed_steps(lib, db, opts, steps, warmup)
 
+    note("timed steps")
     step_s, kt = timed(tuned, args.steps, args.warmup)
     gcups = cells / step_s / 1e9
     tuned_score, tuned_end = (x.copy() for x in db.results())
@@ -769,6 +776,7 @@ def main():
     pkt = {}
     variants = {}
     if not args.skip_plain:
+        note("plain mode")
         plain_s, pkt = timed(plain_opts, max(2, args.steps // 2), 1)
         plain_gcups = cells / plain_s / 1e9
         ps, pe = db.results()
@@ -778,6 +786,7 @@ def main():
         # Same batch with the anti-diagonal kernel for the regions above one
         # stripe (the lane-striped kernels keep the shorter ones).
         ad_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_ANTIDIAG)
+        note("anti-diagonal variant")
         ad_s, akt = timed(ad_opts, 2, 1)
         variants["long_antidiag"] = {"value": cells / ad_s / 1e9, "unit": "GCUPS", "ms_per_step": ad_s * 1e3,
                                      "kernels_ms": akt,
@@ -787,6 +796,7 @@ def main():
         # (pipelined stripes), at the tuned cut-off.
         pp_opts = lib.make_opts(flags=lib.FLAG_TIMING, long_kernel=lib.LONG_PIPELINE, pipe_waves=4,
                                 single_max=single_max)
+        note("pipeline variant")
         pp_s, pkt4 = timed(pp_opts, 3, 1)
         variants["long_pipeline_4_waves"] = {"value": cells / pp_s / 1e9, "unit": "GCUPS",
                                              "ms_per_step": pp_s * 1e3, "kernels_ms": pkt4,
@@ -794,15 +804,22 @@ def main():
                                              "kernel": "k_pipe", "single_max": single_max}
 
     if not args.skip_plain:
+        note("early termination")
         variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
+        note("alignment start")
         variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
+        note("warping paths")
         variants["path"] = path_leg(lib, b, lib.make_opts(**extra))
+        note("banded regions")
         variants["banded_regions"] = banded_regions_leg(lib, db, step_s * 1e3)
     if not args.skip_anchored:
+        note("anchored alignment")
         variants["anchored"] = anchored_leg(lib, valu_peak)
     if not args.skip_plain:
+        note("single read")
         variants["single_read"] = single_read_leg(lib)
     if not args.skip_anchored:
+        note("banded chained segments")
         variants["banded"] = banded_leg(lib, valu_peak, lib.make_opts(**extra))
     configs = {}
     if not args.skip_configs:
@@ -810,8 +827,10 @@ def main():
         # 1,024 x 10,000 x 20,000 long-problem stress
         del db
         torch.cuda.empty_cache()
+        note("4,096-pair plain batch")
         configs["plain_batch_4096"] = batch_config_leg(lib, workloads.plain_batch(), "plain_batch_4096_pairs",
                                                       valu_peak, extra, steps=10, warmup=2)
+        note("long stress")
         configs["long_stress_1024"] = batch_config_leg(lib, workloads.long_stress(),
                                                       "long_stress_1024_x_10000_x_20000", valu_peak, extra,
                                                       steps=3, warmup=1, antidiag=True, pipeline=True)
@@ -864,10 +883,12 @@ def main():
         del db
     torch.cuda.empty_cache()
     if args.serving_reads > 0:
+        note("serving")
         out["serving"] = serving_leg(args.serving_reads, args.serving_rate, args.serving_streams, args.serving_slots,
                                      pipe_waves=args.serving_pipe_waves, single_max=args.serving_single_max)
         checks["serving_capped_results_equal"] = out["serving"]["capped"]["results_equal_uncapped"]
     if not args.no_cpu:
+        note("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds, tuned_score, tuned_end)
         checks["oracle_sample_within_tolerance"] = out["cpu_baseline"]["parity"]["within_tolerance"]
     print(json.dumps(out), flush=True)
