@@ -397,9 +397,12 @@ def span_leg(lib, db, opts, steps: int = 3):
 
 def path_leg(lib, b, opts, steps: int = 3):
     """Warping paths (Sec. 2.4) of the true candidate of every read of the
-    uneven batch (3,901 pairs, the ones a mapper would report):
-    rawalign_dtw_path (forward and reverse passes, direction words, trace
-    back) against rawalign_dtw_span alone on the same pairs."""
+    uneven batch (3,901 pairs, the ones a mapper would report), two ways:
+    rawalign_dtw_path alone (forward and reverse passes, direction words,
+    trace back) into a workspace sized for the whole region of every pair;
+    and rawalign_dtw_span, then rawalign_dtw_path with the span outputs
+    given, into a workspace sized from the aligned intervals.  Both must
+    give the same paths."""
     import torch
     tp = b.true_pair[b.true_pair >= 0]
     sub = b.subset(tp)
@@ -433,14 +436,32 @@ def path_leg(lib, b, opts, steps: int = 3):
     span_ms = timed(span)
     path_ms = timed(path)
     l0 = lo[path_off].cpu().numpy()
+    paths_full = (lo.cpu().numpy(), hi.cpu().numpy())
     end = db.end.cpu().numpy().astype(np.int64)
     st = start.cpu().numpy().astype(np.int64)
     rec = l0 >= 0
     L = end - st + 1
     stripes = (L + 2047) // 2048
+    del dirs
+    torch.cuda.empty_cache()
+    # The span's intervals size the workspace exactly; the path call then
+    # skips the span passes.
+    x_off, x_words = lib.path_workspace_exact(sub.q_len, end, st)
+    x_off = torch.from_numpy(x_off).cuda()
+    x_dirs = torch.empty(max(x_words, 1), dtype=torch.int64, device="cuda")
+    given = lib.make_opts(**{k: v for k, v in (opts.as_dict() if opts is not None else {}).items() if k != "flags"},
+                          flags=lib.FLAG_SPAN_GIVEN)
+
+    def path_given():
+        lib.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, x_off, x_dirs, path_off, lo, hi,
+                              db.score, db.end, start, opts=given)
+    given_ms = timed(path_given)
+    same = bool(np.array_equal(lo.cpu().numpy(), paths_full[0]) and np.array_equal(hi.cpu().numpy(), paths_full[1]))
     return {"ms_per_batch": path_ms, "span_only_ms": span_ms, "pairs": n, "paths_recorded": int(rec.sum()),
             "mean_interval_levels": float(np.mean(L[rec])), "max_interval_levels": int(L[rec].max()),
             "direction_bytes": int((rows[rec] * 512 * stripes[rec]).sum()), "workspace_bytes": words * 8,
+            "exact_workspace_bytes": x_words * 8, "path_after_span_ms": given_ms,
+            "exact_workspace_paths_equal": same,
             "entry_point": "rawalign_dtw_path", "workload": "uneven_batch_true_candidates"}
 
 
@@ -810,6 +831,7 @@ def main():
         variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
         note("warping paths")
         variants["path"] = path_leg(lib, b, lib.make_opts(**extra))
+        checks["path_exact_workspace_paths_equal"] = variants["path"]["exact_workspace_paths_equal"]
         note("banded regions")
         variants["banded_regions"] = banded_regions_leg(lib, db, step_s * 1e3)
     if not args.skip_anchored:

@@ -79,6 +79,9 @@ extern "C" {
 
 /* opts.flags */
 #define RAWALIGN_FLAG_TIMING 1      /* record hipEvents around every kernel (rawalign_last_timing) */
+#define RAWALIGN_FLAG_SPAN_GIVEN 2  /* rawalign_dtw_path only: out_score, out_end and out_start already hold
+                                       rawalign_dtw_span's result for these pairs; its two passes are skipped
+                                       (a caller that sized the direction workspace from those intervals) */
 
 typedef struct rawalign_opts {
     int32_t mode;               /* RAWALIGN_MODE_* */
@@ -305,12 +308,18 @@ int rawalign_dtw_span(const float *q, int64_t q_size, const int64_t *q_off, cons
  *              for an interval of L = e - s + 1 levels, S = ceil(L / 2048)
  *              (2 bits per cell and a stripe edge).  The interval is at most
  *              m levels, so n * (64 * ceil(m / 2048) + 1) words always
- *              suffice.  A pair whose range does not hold its interval gets
- *              -4 in every entry.  The ranges of the pairs of one call must
- *              not overlap.
+ *              suffice; a caller that first calls rawalign_dtw_span can size
+ *              every range from its interval exactly and pass
+ *              RAWALIGN_FLAG_SPAN_GIVEN with that call's outputs.  A pair
+ *              whose range does not hold its interval gets -4 in every
+ *              entry.  The ranges of the pairs of one call must not overlap.
  *   Pairs without an alignment get their end sentinel in every entry (-1
  *   empty region, -2 invalid slice); an empty query has no entries.
  *   Entries of a pair whose range leaves [0, path_size) are not written.
+ *   opts->flags & RAWALIGN_FLAG_SPAN_GIVEN: out_score, out_end and
+ *   out_start are inputs, the result of rawalign_dtw_span on the same pairs
+ *   (an end or start that no alignment of the pair can have gets -2 in
+ *   every entry); the span passes are skipped.
  *   Other arguments, opts and errors as in rawalign_dtw_span; beyond that
  *   call's scratch this entry point allocates nothing.  One wave per pair
  *   records the directions stripe by stripe in the lane-striped order of the

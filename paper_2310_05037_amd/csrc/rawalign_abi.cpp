@@ -776,8 +776,24 @@ int rawalign_dtw_path(const float *q, int64_t q_size, const int64_t *q_off, cons
     if (n_pairs > 0 && (!dir_off || !path_off || !path_lo || !path_hi))
         return fail(RAWALIGN_EINVAL, "null pointer argument: dir_off, path_off, path_lo and path_hi are required");
     if (n_pairs > 0 && dir_size > 0 && !dirs) return fail(RAWALIGN_EINVAL, "null pointer argument: dirs");
-    int rc = rawalign_dtw_span(q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
-                               out_start, stream, opts);
+    // RAWALIGN_FLAG_SPAN_GIVEN belongs to this entry point alone: the span
+    // passes (when run) see the other fields.
+    const bool given = opts && (opts->flags & RAWALIGN_FLAG_SPAN_GIVEN);
+    rawalign_opts o = effective_opts(opts);
+    o.flags &= ~RAWALIGN_FLAG_SPAN_GIVEN;
+    int rc;
+    if (given) {
+        // out_score / out_end / out_start hold a span result; the path
+        // kernels check every interval against its pair before use.
+        rc = check_opts(o);
+        if (rc) return rc;
+        rc = check_call(Call{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end, nullptr,
+                             0, nullptr, nullptr, (hipStream_t)stream});
+        if (!rc && n_pairs > 0 && !out_start) rc = fail(RAWALIGN_EINVAL, "null pointer argument: out_start");
+    } else {
+        rc = rawalign_dtw_span(q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
+                               out_start, stream, opts ? &o : nullptr);
+    }
     if (rc || n_pairs == 0) return rc;
     ra::PathArgs pa;
     pa.q = q;

@@ -31,6 +31,7 @@ LONG_STRIPED = 0
 LONG_ANTIDIAG = 1
 LONG_PIPELINE = 2
 FLAG_TIMING = 1
+FLAG_SPAN_GIVEN = 2   # rawalign_dtw_path: the span outputs are inputs (see path_workspace_exact)
 
 # Every symbol include/rawalign.h declares.
 EXPORTS = (
@@ -247,6 +248,22 @@ def path_workspace(q_len, r_len):
     n = np.maximum(np.asarray(q_len, dtype=np.int64), 0)
     m = np.maximum(np.asarray(r_len, dtype=np.int64), 1)
     words = n * (64 * ((m + 2047) // 2048) + 1)
+    off = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.int64)
+    return off, int(words.sum())
+
+
+def path_workspace_exact(q_len, out_end, out_start):
+    """(dir_off, words) of a direction workspace sized from the intervals of
+    a rawalign_dtw_span call: n * (64 * ceil(L / 2048) + 1) 64-bit words for
+    a pair aligned over L = end - start + 1 levels, none for a pair without
+    an alignment.  Pass it to rawalign_dtw_path with FLAG_SPAN_GIVEN and the
+    same span outputs."""
+    n = np.maximum(np.asarray(q_len, dtype=np.int64), 0)
+    e = np.asarray(out_end, dtype=np.int64)
+    st = np.asarray(out_start, dtype=np.int64)
+    ok = (e >= 0) & (st >= 0) & (st <= e)
+    L = np.where(ok, e - st + 1, 0)
+    words = np.where(ok, n * (64 * ((L + 2047) // 2048) + 1), 0)
     off = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.int64)
     return off, int(words.sum())
 

@@ -161,3 +161,54 @@ def test_path_single_read_and_uneven_batch_sample(L):
     sub = u.subset(pick)
     res = _gpu_path(L, sub)
     _check(sub, res, range(sub.n_pairs))
+
+
+def test_path_after_span_exact_workspace(L):
+    """rawalign_dtw_span, then rawalign_dtw_path with FLAG_SPAN_GIVEN into a
+    workspace sized from the span's intervals (path_workspace_exact): the
+    same scores, ends, starts and level ranges as the path call alone into
+    the region-sized workspace, in far fewer words; a pair whose exact range
+    (the last one in the workspace) is one word short gets -4 in every entry
+    while the others are unchanged;
+    pairs without an alignment take no words."""
+    import torch
+    rng = np.random.default_rng(905)
+    spans = [1, 64, 300, 1000, 2049, 3000, 5000, 40, 700]
+    b = _embedded(rng, spans, "path_exact", dwell_p=0.5)
+    b.r_len[7] = 0                                   # empty region: no alignment, no words
+    ref = _gpu_path(L, b)
+    s0, e0, st0, lo0, hi0, off = ref
+    db = L.DeviceBatch(b)
+    start = torch.empty(b.n_pairs, dtype=torch.int32, device="cuda")
+    L.rawalign_dtw_span(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, db.score, db.end, start)
+    end_np, st_np = db.end.cpu().numpy(), start.cpu().numpy()
+    x_off, x_words = L.path_workspace_exact(b.q_len, end_np, st_np)
+    full_off, full_words = L.path_workspace(b.q_len, b.r_len)
+    assert x_words < full_words
+    assert x_off[7] == x_off[8] if b.n_pairs > 8 else True   # the empty-region pair takes no words
+    opts = L.make_opts(flags=L.FLAG_SPAN_GIVEN)
+    # the pair whose range comes last in the workspace (the check is against
+    # the workspace's end; ranges of one call never overlap)
+    last = int(np.flatnonzero((e0 >= 0) & (b.q_len > 0))[-1])
+    assert x_off[last] == max(int(x_off[p]) for p in range(b.n_pairs) if e0[p] >= 0)
+    for short in (None, last):
+        dirs = torch.empty(max(x_words, 1), dtype=torch.int64, device="cuda")
+        o = x_off.copy()
+        if short is not None:
+            dirs = dirs[:x_words - 1]   # that range ends one word early
+        lo = torch.full((len(lo0),), -7, dtype=torch.int32, device="cuda")
+        hi = torch.full((len(lo0),), -7, dtype=torch.int32, device="cuda")
+        print(f"  gpu: path after span, exact workspace, short={short}", flush=True)
+        L.rawalign_dtw_path(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, torch.from_numpy(o).cuda(),
+                            dirs, torch.from_numpy(off).cuda(), lo, hi, db.score, db.end, start, opts=opts)
+        torch.cuda.synchronize()
+        glo, ghi = lo.cpu().numpy(), hi.cpu().numpy()
+        assert np.array_equal(db.score.cpu().numpy().view(np.uint32), s0.view(np.uint32))
+        assert np.array_equal(db.end.cpu().numpy(), e0) and np.array_equal(start.cpu().numpy(), st0)
+        for p in range(b.n_pairs):
+            n = int(b.q_len[p])
+            seg = slice(off[p], off[p] + n)
+            if short is not None and p == short:
+                assert (glo[seg] == -4).all() and (ghi[seg] == -4).all()
+            else:
+                assert np.array_equal(glo[seg], lo0[seg]) and np.array_equal(ghi[seg], hi0[seg]), p
