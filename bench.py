@@ -705,6 +705,8 @@ def main():
                     help="leave out the 4,096-pair plain batch and the long-problem stress legs")
     ap.add_argument("--only-path", action="store_true",
                     help="run only the warping-path leg and print its JSON (for profiling runs)")
+    ap.add_argument("--only-single-read", action="store_true",
+                    help="run only the single-read latency leg and print its JSON")
     ap.add_argument("--only-banded", action="store_true",
                     help="run only the banded-DTW leg and print its JSON (for profiling runs)")
     ap.add_argument("--only-configs", action="store_true",
@@ -748,6 +750,9 @@ def main():
     valu_peak = cus * LANES_PER_CU * CLOCK_HZ
     if args.only_anchored:
         print(json.dumps({"anchored": anchored_leg(lib, valu_peak, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
+    if args.only_single_read:
+        print(json.dumps({"single_read": single_read_leg(lib)}), flush=True)
         return
     if args.only_path:
         print(json.dumps({"path": path_leg(lib, workloads.uneven_batch(), None, steps=args.steps)}), flush=True)

@@ -401,7 +401,7 @@ RA_DEV void sweep(const PairView &pv, int col_base, float *edge, float corner, f
             ea = uload(ers, t + 2, nm1);                                                     \
             eb = uload(ers, t + 3, nm1);                                                     \
         }                                                                                    \
-        if (ILP2)                                                                            \
+        if constexpr (ILP2)                                                                  \
             two_steps2<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, qo, q0, q1, E0, E1, e0, e1, edge); \
         else                                                                                 \
             two_steps<C, MASKED, EIN, EOUT>(t, n, lane, rv, A, B, qv, q0, q1, E0, E1, e0, e1, edge); \
