@@ -35,11 +35,18 @@
 //   * rings and edge buffers are split into two halves of four floats per
 //     tile, so the 16-byte reads and writes of neighbouring threads fall on
 //     consecutive banks.
-// Every thread runs the same step loop with the same bounds, so every thread
-// reaches every barrier.  Tiles past the query (rows >= n) are computed and
-// discarded.  The thread holding row n-1 tracks the running minimum of the
-// last row (columns increase along its tiles, so a strict < keeps the
-// smallest column on ties).
+//   * inside a tile the cells are taken in anti-diagonal order as well, so
+//     each cell's min3 -> add pair has independent cells between it and the
+//     next use of its result.
+// Every thread runs the same step loops with the same bounds, so every
+// thread reaches every barrier.  Tiles past the query (rows >= n) are
+// computed and discarded, except on the thread t_l that holds row n-1: from
+// the step at which it enters the last row block, its rows below n-1 take a
+// weight of 0 on the distance term, which turns them into prefix minima of
+// row n-1 (the same minimum at the same first column), and it stores the
+// last row of each tile into the row buffer.  After the loop the workgroup
+// scans that row for its minimum and first column.  Without rows below n-1
+// on thread t_l (n-1 is its last row) no step needs the weights.
 #include "dtw_device.h"
 
 namespace ra {
@@ -165,6 +172,47 @@ RA_DEV void ad_rows_load(const PairView &pv, const AdShape &a, int block, float 
     }
 }
 
+// The cell with a weight on the distance term: c = 1 is the recurrence
+// itself (the product is exact, so the fused add rounds as the plain add
+// does); c = 0 gives min(NW, N, W), a row that carries the prefix minimum of
+// the row above.
+RA_DEV float cell_w(float qv, float c, float rv, float diag, float up, float left) {
+    return __builtin_fmaf(fabsf(qv - rv), c, fminf(fminf(diag, up), left));
+}
+
+// One R x K tile in anti-diagonal order.  above[] holds the row above the
+// tile on entry and the tile's last row on exit; left[] the column left of
+// the tile on entry and its last column on exit; upleft the north-west
+// corner.  The cells (s, k) with s + k = d depend only on diagonals d-1 and
+// d-2, so each cell's min3 -> add pair is followed by independent cells of
+// the same diagonal instead of waiting on its own result.  WEIGHTED: row s
+// takes the weight cv[s] on its distance term.
+template <int R, bool WEIGHTED>
+RA_DEV void ad_tile(const float (&qv)[R], const float (&cv)[R], const float (&lv)[kAdK], float (&above)[kAdK],
+                    float (&left)[R], float upleft) {
+    constexpr int K = kAdK;
+    float v[R][K];
+#pragma unroll
+    for (int d = 0; d < R + K - 1; ++d) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int k = d - s;
+            if (k < 0 || k >= K) continue;
+            const float n_ = s == 0 ? above[k] : v[s - 1][k];
+            const float w = k == 0 ? left[s] : v[s][k - 1];
+            const float nw = s == 0 ? (k == 0 ? upleft : above[k - 1]) : (k == 0 ? left[s - 1] : v[s - 1][k - 1]);
+            if constexpr (WEIGHTED)
+                v[s][k] = cell_w(qv[s], cv[s], lv[k], nw, n_, w);
+            else
+                v[s][k] = cell(qv[s], lv[k], nw, n_, w);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) above[k] = v[R - 1][k];
+#pragma unroll
+    for (int s = 0; s < R; ++s) left[s] = v[s][K - 1];
+}
+
 template <int R>
 RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdShape &a, float &best, int &bj) {
     constexpr int K = kAdK;
@@ -197,6 +245,15 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     // within row block rb (negative while the wavefront has not arrived).
     int g = -t, rb = 0, b = -t;
     const int E_end = a.last_tile + a.t_l;   // last step with work (thread t_l, last tile)
+    // First step at which thread t_l is in the last row block.  From there
+    // on, thread t_l's rows past query row n-1 take weight 0, so the last row
+    // of its tiles is row n-1 itself or its prefix minimum (the same minimum
+    // at the same first column), and it stores that row into the row buffer
+    // (free in the last block: its row above was staged before).
+    const int E_track = (a.blocks - 1) * a.stride + a.t_l;
+    float cv[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) cv[s] = 1.0f;
     // LDS offsets of the edge read and write that do not depend on the step.
     const int rd_edge = kAdEdge + 4 * (t - 1);
     const int wr_edge = kAdEdge + 4 * t;
@@ -206,7 +263,9 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     // in [0, kAdLvHalf) for the negative tiles of the wavefront's arrival).
     int lvi = ((4 * (1 - t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf;
     ld8(f, kAdLv + ((4 * (-t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf, lvn);
-    for (int E = 0; E <= E_end; ++E) {
+    // One step: this thread's tile g = E - t, the edge handed to thread t+1,
+    // the staging of every 32nd step, one barrier.
+    auto step = [&](const int E, auto weighted) __attribute__((always_inline)) {
         // Row above the first own row: the left neighbour's last row at
         // step E-1 (lane t-1 of this wave, or lane 63 of the wave before
         // through the boundary slot); for thread 0 the staged row above.
@@ -231,35 +290,11 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         }
         const bool live = g >= 0 && b < a.tiles && g <= a.last_tile;
         if (live) {
-            const bool track = rb == a.blocks - 1 && t == a.t_l;
             const int j0 = K * b;
-            float diag = upleft;
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-                float w = left[s];
-                float d = diag;
-                diag = w;   // D(row, j0-1): the next row's north-west
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float n_ = above[k];
-                    const float v = cell(qv[s], lv[k], d, n_, w);
-                    d = n_;
-                    above[k] = v;
-                    w = v;
-                }
-                left[s] = w;
-                if (s == a.s_l && track) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        if (j0 + k < m && above[k] < best) {
-                            best = above[k];
-                            bj = j0 + k;
-                        }
-                    }
-                }
-            }
-            if (t == kAdThreads - 1 && rb < a.blocks - 1) {
-                // Last row of the block: the row above of block rb+1.
+            ad_tile<R, decltype(weighted)::value>(qv, cv, lv, above, left, upleft);
+            if ((t == kAdThreads - 1 && rb < a.blocks - 1) || (t == a.t_l && rb == a.blocks - 1)) {
+                // Last row of the block (the row above of block rb+1), or
+                // thread t_l's last row in the last block.
                 if (j0 + K <= m) {
                     *reinterpret_cast<float4 *>(prow + j0) = make_float4(above[0], above[1], above[2], above[3]);
                     *reinterpret_cast<float4 *>(prow + j0 + 4) = make_float4(above[4], above[5], above[6], above[7]);
@@ -294,6 +329,43 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
             ++rb;
         }
         lds_barrier();
+    };
+    // Weights are needed only below row n-1 within thread t_l's tile.
+    const int E_w = a.s_l == R - 1 ? E_end + 1 : E_track;
+    int E = 0;
+    for (; E < E_w; ++E) step(E, std::false_type{});
+#pragma unroll
+    for (int s = 0; s < R; ++s) cv[s] = t == a.t_l && s > a.s_l ? 0.0f : 1.0f;
+    for (; E <= E_end; ++E) step(E, std::true_type{});
+    // Minimum of the stored row and its first column: a strided scan per
+    // thread (four loads in flight; columns increase, so a strict < keeps
+    // the first), then across the wave and the four waves.
+    __syncthreads();
+    float bv = kInf;
+    int bc = 0x7fffffff;
+    for (int j0 = t; j0 < m; j0 += 4 * kAdThreads) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = j0 + u * kAdThreads < m ? prow[j0 + u * kAdThreads] : kInf;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u] < bv) {
+                bv = v[u];
+                bc = j0 + u * kAdThreads;
+            }
+        }
+    }
+    wave_min(bv, bc);
+    float *red = f + kAdEdge;
+    if (lane == 0) {
+        red[wave] = bv;
+        reinterpret_cast<int *>(red)[4 + wave] = bc;
+    }
+    __syncthreads();
+    if (t == 0) {
+        best = red[0];
+        bj = reinterpret_cast<const int *>(red)[4];
+        for (int w = 1; w < kAdThreads / 64; ++w) take_min(best, bj, red[w], reinterpret_cast<const int *>(red)[4 + w]);
     }
 }
 
@@ -326,18 +398,13 @@ __global__ __launch_bounds__(kAdThreads) __attribute__((amdgpu_waves_per_eu(5, 5
         // under the step-count model (uniform across the workgroup).
         const AdShape a2 = ad_shape(pv.n, pv.m, 2), a4 = ad_shape(pv.n, pv.m, 4), a8 = ad_shape(pv.n, pv.m, 8);
         const long long c2 = ad_cost(a2), c4 = ad_cost(a4), c8 = ad_cost(a8);
-        int tl;
-        if (c8 <= c4 && c8 <= c2) {
+        if (c8 <= c4 && c8 <= c2)
             antidiag_pair<8>(pv, prow, f, a8, best, bj);
-            tl = a8.t_l;
-        } else if (c4 <= c2) {
+        else if (c4 <= c2)
             antidiag_pair<4>(pv, prow, f, a4, best, bj);
-            tl = a4.t_l;
-        } else {
+        else
             antidiag_pair<2>(pv, prow, f, a2, best, bj);
-            tl = a2.t_l;
-        }
-        if (threadIdx.x == tl) {
+        if (threadIdx.x == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;
         }

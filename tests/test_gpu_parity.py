@@ -200,6 +200,35 @@ def test_antidiag_short_regions_padded_stride(L):
     assert np.array_equal(s.view(np.uint32), s3.view(np.uint32)) and np.array_equal(e, e3)
 
 
+def test_antidiag_ties_first_column(L):
+    """Small-integer queries and levels, so the last row holds the same
+    minimum at many columns, within a tile and across tiles and row blocks.
+    The query lengths put row n-1 at every row slot of its thread for 2, 4
+    and 8 rows per thread (the slot below which the kernel's weight-0 rows
+    carry the prefix minimum) and at the last slot (no weight-0 rows).
+    Score bits and first column equal the float oracle's."""
+    from oracle import oracle
+    rng = np.random.default_rng(12)
+    ns = [1, 2, 3, 255, 256, 511, 600, 601, 602, 603, 1023, 1024, 1500, 1501, 1502, 1503, 2047, 2048, 2049,
+          2600, 2601, 2602, 2603, 2604, 2605, 2606, 2607, 3072, 4095, 4096, 4097, 5003, 6143, 6144]
+    ms = [4097 + int(rng.integers(0, 5000)) for _ in ns]
+    reads = [rng.integers(0, 3, n).astype(np.float32) for n in ns]
+    r = rng.integers(0, 3, sum(ms)).astype(np.float32)
+    pairs, off = [], 0
+    for i, m in enumerate(ms):
+        pairs.append((i, off, m, False))
+        off += m
+    b = W._pack("antidiag_ties", reads, pairs, r, {})
+    for kw in (dict(long_kernel=L.LONG_ANTIDIAG), dict(long_kernel=L.LONG_ANTIDIAG, mode=L.MODE_PLAIN)):
+        print(f"  gpu: antidiag ties {kw}", flush=True)
+        s, e = _run(L, b, **kw)
+        for p in range(b.n_pairs):
+            q = b.q[b.q_off[p]:b.q_off[p] + b.q_len[p]]
+            rr = b.r[b.r_off[p]:b.r_off[p] + b.r_len[p]]
+            c32, e32 = oracle.dtw_f32(q, rr)
+            assert s[p].view(np.uint32) == np.float32(c32).view(np.uint32) and e[p] == e32, (p, ns[p], ms[p])
+
+
 def test_antidiag_uneven_batch(L):
     """The 100,000-pair uneven batch with the anti-diagonal kernel on every
     region above one stripe (at both cut-offs) equals the default path."""
