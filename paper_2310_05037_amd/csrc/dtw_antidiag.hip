@@ -257,12 +257,14 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     // LDS offsets of the edge read and write that do not depend on the step.
     const int rd_edge = kAdEdge + 4 * (t - 1);
     const int wr_edge = kAdEdge + 4 * t;
-    float lvn[K];
+    float lv[K];   // levels of this step's tile, loaded at the end of the step before
+    bool store = false;   // this thread stores its tiles' last row (set at each block start)
     lds_barrier();
-    // Level-ring offset of the tile each step prefetches, tile g + 1 (kept
-    // in [0, kAdLvHalf) for the negative tiles of the wavefront's arrival).
+    // Level-ring offset of the tile each step loads for the next, tile g + 1
+    // (kept in [0, kAdLvHalf) for the negative tiles of the wavefront's
+    // arrival).
     int lvi = ((4 * (1 - t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf;
-    ld8(f, kAdLv + ((4 * (-t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf, lvn);
+    ld8(f, kAdLv + ((4 * (-t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf, lv);
     // One step: this thread's tile g = E - t, the edge handed to thread t+1,
     // the staging of every 32nd step, one barrier.
     auto step = [&](const int E, auto weighted) __attribute__((always_inline)) {
@@ -274,11 +276,6 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         float above[K];
         ld8(f, rd, above);
         const float up_last = above[K - 1];   // north-west of the next tile's first row
-        float lv[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) lv[k] = lvn[k];
-        ld8(f, kAdLv + lvi, lvn);
-        lvi = lvi + 4 == kAdLvHalf ? 0 : lvi + 4;
         if (b == 0) {
             // A new row block: column -1 is +inf, query rows of block rb.
 #pragma unroll
@@ -287,12 +284,13 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
                 qv[s] = qrow[s];
             }
             upleft = kInf;
+            store = (t == kAdThreads - 1 && rb < a.blocks - 1) || (t == a.t_l && rb == a.blocks - 1);
         }
-        const bool live = g >= 0 && b < a.tiles && g <= a.last_tile;
+        const bool live = (unsigned)g <= (unsigned)a.last_tile && b < a.tiles;
         if (live) {
             const int j0 = K * b;
             ad_tile<R, decltype(weighted)::value>(qv, cv, lv, above, left, upleft);
-            if ((t == kAdThreads - 1 && rb < a.blocks - 1) || (t == a.t_l && rb == a.blocks - 1)) {
+            if (store) {
                 // Last row of the block (the row above of block rb+1), or
                 // thread t_l's last row in the last block.
                 if (j0 + K <= m) {
@@ -307,6 +305,9 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         }
         upleft = up_last;
         st8(f, lane == 63 ? kAdBnd + ((E & 1) * 4 + wave) * 4 : wr_edge, above);
+        // The next step's levels: this barrier's LDS wait covers the load.
+        ld8(f, kAdLv + lvi, lv);
+        lvi = lvi + 4 == kAdLvHalf ? 0 : lvi + 4;
         if ((E & (kAdChunk - 1)) == kAdChunk - 1) {
             const int c = E / kAdChunk;
             ad_stage_store(f, staged, c + 2);
