@@ -162,6 +162,15 @@ RA_DEV void st8(float *f, int o, const float (&v)[kAdK]) {
     *reinterpret_cast<float4 *>(f + kAdHalf + o) = make_float4(v[4], v[5], v[6], v[7]);
 }
 
+// The same at a byte offset (offsets that a step selects per lane).
+RA_DEV void ld8b(const float *f, int ob, float (&v)[kAdK]) {
+    ld8(reinterpret_cast<const float *>(reinterpret_cast<const char *>(f) + ob), 0, v);
+}
+
+RA_DEV void st8b(float *f, int ob, const float (&v)[kAdK]) {
+    st8(reinterpret_cast<float *>(reinterpret_cast<char *>(f) + ob), 0, v);
+}
+
 // Query rows R t .. R t + R-1 of row block `block` (0 past the query).
 template <int R>
 RA_DEV void ad_rows_load(const PairView &pv, const AdShape &a, int block, float (&q)[R]) {
@@ -242,8 +251,9 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     }
     float upleft = kInf;
     // Stream position of this thread's tile: g = E - t, b = column tile
-    // within row block rb (negative while the wavefront has not arrived).
-    int g = -t, rb = 0, b = -t;
+    // within row block rb.  b starts at S - t so that it reaches S (the
+    // start of block 0) at g = 0; a step that finds b == S starts a block.
+    int rb = -1, b = a.stride - t;
     const int E_end = a.last_tile + a.t_l;   // last step with work (thread t_l, last tile)
     // First step at which thread t_l is in the last row block.  From there
     // on, thread t_l's rows past query row n-1 take weight 0, so the last row
@@ -254,9 +264,11 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     float cv[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) cv[s] = 1.0f;
-    // LDS offsets of the edge read and write that do not depend on the step.
-    const int rd_edge = kAdEdge + 4 * (t - 1);
-    const int wr_edge = kAdEdge + 4 * t;
+    // LDS byte offsets of the edge read and write of lanes 1..63 and 0..62
+    // (step-independent); lanes 0 and 63 take a wave-uniform slot per step.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int rd_edge = 4 * (kAdEdge + 4 * (t - 1));
+    const int wr_edge = 4 * (kAdEdge + 4 * t);
     float lv[K];   // levels of this step's tile, loaded at the end of the step before
     bool store = false;   // this thread stores its tiles' last row (set at each block start)
     lds_barrier();
@@ -271,13 +283,14 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         // Row above the first own row: the left neighbour's last row at
         // step E-1 (lane t-1 of this wave, or lane 63 of the wave before
         // through the boundary slot); for thread 0 the staged row above.
-        int rd = rd_edge;
-        if (lane == 0) rd = wave == 0 ? kAdUp + ((4 * E) & (kAdUpHalf - 1)) : kAdBnd + (((E - 1) & 1) * 4 + wave - 1) * 4;
+        const int rd0 = 4 * (wv == 0 ? kAdUp + ((4 * E) & (kAdUpHalf - 1)) : kAdBnd + (((E - 1) & 1) * 4 + wv - 1) * 4);
         float above[K];
-        ld8(f, rd, above);
+        ld8b(f, lane == 0 ? rd0 : rd_edge, above);
         const float up_last = above[K - 1];   // north-west of the next tile's first row
-        if (b == 0) {
+        if (b == a.stride) {
             // A new row block: column -1 is +inf, query rows of block rb.
+            b = 0;
+            ++rb;
 #pragma unroll
             for (int s = 0; s < R; ++s) {
                 left[s] = kInf;
@@ -286,6 +299,7 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
             upleft = kInf;
             store = (t == kAdThreads - 1 && rb < a.blocks - 1) || (t == a.t_l && rb == a.blocks - 1);
         }
+        const int g = E - t;
         const bool live = (unsigned)g <= (unsigned)a.last_tile && b < a.tiles;
         if (live) {
             const int j0 = K * b;
@@ -304,7 +318,7 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
             }
         }
         upleft = up_last;
-        st8(f, lane == 63 ? kAdBnd + ((E & 1) * 4 + wave) * 4 : wr_edge, above);
+        st8b(f, lane == 63 ? 4 * (kAdBnd + ((E & 1) * 4 + wv) * 4) : wr_edge, above);
         // The next step's levels: this barrier's LDS wait covers the load.
         ld8(f, kAdLv + lvi, lv);
         lvi = lvi + 4 == kAdLvHalf ? 0 : lvi + 4;
@@ -323,12 +337,7 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
                 ++q_next;
             }
         }
-        ++g;
         ++b;
-        if (b == a.stride) {
-            b = 0;
-            ++rb;
-        }
         lds_barrier();
     };
     // Weights are needed only below row n-1 within thread t_l's tile.
