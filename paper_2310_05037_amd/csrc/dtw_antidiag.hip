@@ -60,7 +60,10 @@ constexpr int kAdUpChunks = 4;                               // row-above ring: 
 constexpr int kAdLvHalf = 4 * kAdChunk * kAdLvChunks;        // floats per half of the level ring
 constexpr int kAdUpHalf = 4 * kAdChunk * kAdUpChunks;
 constexpr int kAdMinStride = kAdThreads + 4 * kAdChunk;      // 384 tiles
-constexpr int kAdStepCost = 24;                              // per-step overhead in VALU slots (cost model)
+// Per-step overhead in VALU slots of the cost model: about 28 VALU of edge,
+// level and index work per step at R = 8, plus the barrier; 48 picks R best
+// on mixed shapes (24 and 96 both measured slower).
+constexpr int kAdStepCost = 48;
 
 // LDS layout, in floats.  Every 8-value access (a tile's levels, a row
 // segment) is two 16-byte halves at the same offset in half 0 and half 1,
@@ -275,7 +278,7 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
     // Level-ring offset of the tile each step loads for the next, tile g + 1
     // (kept in [0, kAdLvHalf) for the negative tiles of the wavefront's
     // arrival).
-    int lvi = ((4 * (1 - t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf;
+    int lvi = 4 * (((4 * (1 - t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf);   // bytes
     ld8(f, kAdLv + ((4 * (-t)) % kAdLvHalf + kAdLvHalf) % kAdLvHalf, lv);
     // One step: this thread's tile g = E - t, the edge handed to thread t+1,
     // the staging of every 32nd step, one barrier.
@@ -320,8 +323,8 @@ RA_DEV void antidiag_pair(const PairView &pv, float *prow, float *f, const AdSha
         upleft = up_last;
         st8b(f, lane == 63 ? 4 * (kAdBnd + ((E & 1) * 4 + wv) * 4) : wr_edge, above);
         // The next step's levels: this barrier's LDS wait covers the load.
-        ld8(f, kAdLv + lvi, lv);
-        lvi = lvi + 4 == kAdLvHalf ? 0 : lvi + 4;
+        ld8b(f, 4 * kAdLv + lvi, lv);
+        lvi = lvi + 16 == 4 * kAdLvHalf ? 0 : lvi + 16;
         if ((E & (kAdChunk - 1)) == kAdChunk - 1) {
             const int c = E / kAdChunk;
             ad_stage_store(f, staged, c + 2);
