@@ -785,6 +785,13 @@ def main():
         tune_ms = (time.perf_counter() - t0) * 1e3
         extra = {k: v for k, v in best.as_dict().items() if k != "flags"}
     tuned = lib.make_opts(flags=lib.FLAG_TIMING, **extra)
+    # The anti-diagonal kernel runs plain batches only: the legs that call
+    # other entry points (alignment start, paths, early termination, banded)
+    # take the striped kernel at its default grid when the tuner chose it,
+    # as the library does for calls that inherit the tuned setting.
+    extra_other = dict(extra)
+    if int(extra_other.get("long_kernel", 0)) == lib.LONG_ANTIDIAG:
+        extra_other.update(long_kernel=lib.LONG_STRIPED, long_waves_per_cu=0)
     single_max = int(extra.get("single_max") or 4096)
     rc = route_cells(b, single_max)
     long_name = {1: "k_antidiag", 2: "k_pipe"}.get(int(extra.get("long_kernel", 0)), "k_multi")
@@ -831,11 +838,11 @@ def main():
 
     if not args.skip_plain:
         note("early termination")
-        variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra))
+        variants["early_termination"] = bnb_leg(lib, b, lib.make_opts(**extra_other))
         note("alignment start")
-        variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra))
+        variants["alignment_start"] = span_leg(lib, db, lib.make_opts(**extra_other))
         note("warping paths")
-        variants["path"] = path_leg(lib, b, lib.make_opts(**extra))
+        variants["path"] = path_leg(lib, b, lib.make_opts(**extra_other))
         checks["path_exact_workspace_paths_equal"] = variants["path"]["exact_workspace_paths_equal"]
         note("banded regions")
         variants["banded_regions"] = banded_regions_leg(lib, db, step_s * 1e3)
@@ -847,7 +854,7 @@ def main():
         variants["single_read"] = single_read_leg(lib)
     if not args.skip_anchored:
         note("banded chained segments")
-        variants["banded"] = banded_leg(lib, valu_peak, lib.make_opts(**extra))
+        variants["banded"] = banded_leg(lib, valu_peak, lib.make_opts(**extra_other))
     configs = {}
     if not args.skip_configs:
         # the other batch workloads: the 4,096-pair plain batch and the

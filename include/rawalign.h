@@ -422,11 +422,16 @@ int rawalign_chain_decide(const float *gap_cost, int64_t n_gaps, const int64_t *
  *   1. the kernel shape: the single-stripe cut-off (single_max 4096 or 2048,
  *      i.e. 34..64 columns per lane on one stripe or 17..32 on two for
  *      regions of 2049..4096 levels) times the long-route kernel and its
- *      workgroup shape (one wave per pair, or 2, 4 or 8 waves sharing each
- *      pair: RAWALIGN_LONG_PIPELINE);
+ *      workgroup shape (one wave per pair, 2, 4 or 8 waves sharing each
+ *      pair: RAWALIGN_LONG_PIPELINE, or one 256-thread workgroup per pair:
+ *      RAWALIGN_LONG_ANTIDIAG);
  *   2. at that shape: one or three streams, and each route's persistent grid
  *      at or below its occupancy limit.
  * Every candidate returns the same bits, so the choice affects time only.
+ * The anti-diagonal kernel serves plain batches only: calls of the other
+ * entry points that inherit a tuned setting naming it (opts NULL) take the
+ * striped kernel at its default grid instead; explicit opts naming it are
+ * rejected there as before.
  * If cache_path is not NULL the result is also written there as JSON keyed
  * by device name, gfx architecture and library version (rawalign_load_tuning
  * reads it back).  `best` (host, may be NULL) receives it.  The batch should

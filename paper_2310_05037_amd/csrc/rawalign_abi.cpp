@@ -457,7 +457,12 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
     return RAWALIGN_OK;
 }
 
-rawalign_opts effective_opts(const rawalign_opts *opts) {
+// The caller's opts, else the device's tuned setting, else the defaults.
+// The anti-diagonal kernel runs plain subsequence batches only; a call of
+// another kind (antidiag_ok false) that inherits it from the tuned setting
+// takes the striped kernel at its default grid instead (explicit opts are
+// checked, not changed).
+rawalign_opts effective_opts(const rawalign_opts *opts, bool antidiag_ok = false) {
     rawalign_opts o;
     if (opts) return *opts;
     defaults(o);
@@ -466,6 +471,10 @@ rawalign_opts effective_opts(const rawalign_opts *opts) {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(dev);
         if (it != g_tuned.end()) o = it->second;
+    }
+    if (!antidiag_ok && o.long_kernel == RAWALIGN_LONG_ANTIDIAG) {
+        o.long_kernel = RAWALIGN_LONG_STRIPED;
+        o.long_waves_per_cu = 0;
     }
     return o;
 }
@@ -536,7 +545,7 @@ int rawalign_dtw_batch_ex(const float *q, int64_t q_size, const int64_t *q_off, 
                           const rawalign_opts *opts) {
     Call c{q, q_size, q_off, q_len, r, r_size, r_off, r_len, n_pairs, out_score, out_end,
            nullptr, 0, nullptr, nullptr, (hipStream_t)stream};
-    return run(c, effective_opts(opts));
+    return run(c, effective_opts(opts, true));
 }
 
 int rawalign_dtw_batch_noalloc(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
@@ -990,15 +999,18 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
     // single-stripe cut-off (2049..4096-level regions on one stripe of
     // 34..64 columns per lane at two waves per SIMD, or on two stripes of
     // 17..32 at four) and the long-route kernel with its workgroup shape
-    // (one wave per pair, or 2, 4 or 8 waves sharing each pair).
+    // (one wave per pair, 2, 4 or 8 waves sharing each pair, or the
+    // anti-diagonal kernel's 256-thread workgroup; waves = 0 below).
     for (int single_max : {4096, 2048}) {
-        for (int waves : {1, 2, 4, 8}) {
+        for (int waves : {1, 2, 4, 8, 0}) {
             rawalign_opts o;
             defaults(o);
             o.single_max = single_max;
             if (waves > 1) {
                 o.long_kernel = RAWALIGN_LONG_PIPELINE;
                 o.pipe_waves = waves;
+            } else if (waves == 0) {
+                o.long_kernel = RAWALIGN_LONG_ANTIDIAG;
             }
             rc = consider(o);
             if (rc) break;
@@ -1007,15 +1019,19 @@ int rawalign_autotune(const float *q, int64_t q_size, const int64_t *q_off, cons
     }
     // Stage 2, at that shape: concurrent or sequential route kernels, and
     // persistent grids at or below each kernel's occupancy limit (waves per
-    // CU; the pipelined kernel counts its waves).
+    // CU; the pipelined kernel counts its waves, the anti-diagonal kernel
+    // its workgroups).
     if (!rc) {
         const rawalign_opts shape = best;
         const bool pipe = shape.long_kernel == RAWALIGN_LONG_PIPELINE;
+        const bool antidiag = shape.long_kernel == RAWALIGN_LONG_ANTIDIAG;
         const int pw = shape.pipe_waves ? shape.pipe_waves : 4;
         const int lo_occ = ra::single_lo_blocks_per_cu(false);
         const int hi_occ = ra::single_hi_blocks_per_cu(false);
-        const int mu_occ = pipe ? ra::pipe_blocks_per_cu(pw, false) * pw : ra::multi_blocks_per_cu(false);
-        const int mu_less = pipe ? mu_occ - pw : mu_occ - 4;
+        const int mu_occ = pipe       ? ra::pipe_blocks_per_cu(pw, false) * pw
+                           : antidiag ? ra::antidiag_blocks_per_cu()
+                                      : ra::multi_blocks_per_cu(false);
+        const int mu_less = pipe ? mu_occ - pw : antidiag ? mu_occ - 1 : mu_occ - 4;
         std::vector<rawalign_opts> cands;
         for (int streams : {1, 3})
             for (int lo : {lo_occ, lo_occ > 4 ? lo_occ - 4 : lo_occ})

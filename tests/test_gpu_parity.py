@@ -362,6 +362,66 @@ def test_autotune_and_tuning_cache(L, tmp_path):
     assert np.array_equal(s0.view(np.uint32), s1.view(np.uint32)) and np.array_equal(e0, e1)
 
 
+def test_tuned_antidiag_setting(L, tmp_path):
+    """A tuned setting that names the anti-diagonal kernel (a tuning cache
+    edited to it) runs plain batches with that kernel (opts NULL equals the
+    explicit setting and the striped kernel), while the alignment-start
+    entry point, inheriting it with opts NULL, takes the striped kernel
+    instead of failing; explicit anti-diagonal opts are still rejected
+    there.  The device's tuned setting is put back to the defaults after."""
+    import json
+    import torch
+    rng = np.random.default_rng(21)
+    ns, ms = [300, 2600, 700, 5000], [5000, 9000, 4500, 4200]
+    reads = [rng.standard_normal(n).astype(np.float32) for n in ns]
+    r = rng.standard_normal(sum(ms)).astype(np.float32)
+    pairs, off = [], 0
+    for i, m in enumerate(ms):
+        pairs.append((i, off, m, False))
+        off += m
+    b = W._pack("tuned_antidiag", reads, pairs, r, {})
+    db = L.DeviceBatch(b)
+    _say(f"  gpu: tuned anti-diagonal setting pairs={b.n_pairs}")
+    cache = str(tmp_path / "tune.json")
+    L.rawalign_autotune(*db.args(), cache_path=cache)   # a cache for this device and library version
+    doc = json.load(open(cache))
+
+    def load_with(**fields):
+        d = dict(doc, **fields)
+        path = str(tmp_path / "edited.json")
+        json.dump(d, open(path, "w"))
+        return L.rawalign_load_tuning(path)
+
+    start = torch.empty(b.n_pairs, dtype=torch.int32, device="cuda")
+
+    def span(opts):
+        L.rawalign_dtw_span(db.q, db.q_off, db.q_len, db.r, db.r_off, db.r_len, db.score, db.end, start,
+                            opts=opts)
+        torch.cuda.synchronize()
+        return db.score.cpu().numpy(), db.end.cpu().numpy(), start.cpu().numpy()
+
+    try:
+        db.run(opts=L.make_opts())
+        s0, e0 = db.results()
+        sp0 = span(L.make_opts())
+        loaded = load_with(long_kernel=L.LONG_ANTIDIAG, long_waves_per_cu=0, pipe_waves=0)
+        assert loaded.long_kernel == L.LONG_ANTIDIAG
+        db.run()   # opts NULL: the tuned anti-diagonal setting
+        s1, e1 = db.results()
+        db.run(opts=L.make_opts(long_kernel=L.LONG_ANTIDIAG, single_max=int(doc["single_max"])))
+        s2, e2 = db.results()
+        for s, e in ((s1, e1), (s2, e2)):
+            assert np.array_equal(s0.view(np.uint32), s.view(np.uint32)) and np.array_equal(e0, e)
+        sp1 = span(None)   # inherits the setting: striped kernel
+        for x, y in zip(sp0, sp1):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+        with pytest.raises(L.RawAlignError):
+            span(L.make_opts(long_kernel=L.LONG_ANTIDIAG))
+    finally:
+        d = L.opts_default().as_dict()
+        load_with(**{k: v for k, v in d.items() if k != "flags"})
+
+
 def test_million_event_query_and_64bit_offsets(L):
     """A single-stripe pair with a query of a million events, and pairs whose
     query and region slices start beyond 2^31 elements (8 GiB arrays), against
