@@ -6,7 +6,7 @@
 // that scheme on one workgroup of 256 threads per pair, kept as the
 // comparison variant of the lane-striped kernel (RAWALIGN_LONG_ANTIDIAG),
 // with the unit of the wavefront widened from one cell to a tile:
-//   * the query rows are taken in blocks of 256 R (R = 2, 4 or 8, chosen per
+//   * the query rows are taken in blocks of 256 R (R = 2 to 8, chosen per
 //     pair from a cost model); thread t owns rows R t .. R t + R-1 of every
 //     block, and the region's columns are cut into tiles of K = 8;
 //   * tiles are numbered in one stream g = rb S + b over (row block rb,
@@ -407,16 +407,28 @@ __global__ __launch_bounds__(kAdThreads) __attribute__((amdgpu_waves_per_eu(5, 5
         float best = kInf;
         int bj = 0x7fffffff;
         // The planner routes only pairs with 1 <= n <= kEdgeCap and regions
-        // above one stripe here.  Rows per thread: the cheapest of 2, 4, 8
-        // under the step-count model (uniform across the workgroup).
-        const AdShape a2 = ad_shape(pv.n, pv.m, 2), a4 = ad_shape(pv.n, pv.m, 4), a8 = ad_shape(pv.n, pv.m, 8);
-        const long long c2 = ad_cost(a2), c4 = ad_cost(a4), c8 = ad_cost(a8);
-        if (c8 <= c4 && c8 <= c2)
-            antidiag_pair<8>(pv, prow, f, a8, best, bj);
-        else if (c4 <= c2)
-            antidiag_pair<4>(pv, prow, f, a4, best, bj);
-        else
-            antidiag_pair<2>(pv, prow, f, a2, best, bj);
+        // above one stripe here.  Rows per thread: the cheapest R of 2..8
+        // under the step-count model (uniform across the workgroup; the
+        // largest R on equal cost).
+        int R = 8;
+        long long cbest = ad_cost(ad_shape(pv.n, pv.m, 8));
+        for (int r = 7; r >= 2; --r) {
+            const long long c = ad_cost(ad_shape(pv.n, pv.m, r));
+            if (c < cbest) {
+                cbest = c;
+                R = r;
+            }
+        }
+        R = __builtin_amdgcn_readfirstlane(R);
+        switch (R) {
+        case 8: antidiag_pair<8>(pv, prow, f, ad_shape(pv.n, pv.m, 8), best, bj); break;
+        case 7: antidiag_pair<7>(pv, prow, f, ad_shape(pv.n, pv.m, 7), best, bj); break;
+        case 6: antidiag_pair<6>(pv, prow, f, ad_shape(pv.n, pv.m, 6), best, bj); break;
+        case 5: antidiag_pair<5>(pv, prow, f, ad_shape(pv.n, pv.m, 5), best, bj); break;
+        case 4: antidiag_pair<4>(pv, prow, f, ad_shape(pv.n, pv.m, 4), best, bj); break;
+        case 3: antidiag_pair<3>(pv, prow, f, ad_shape(pv.n, pv.m, 3), best, bj); break;
+        default: antidiag_pair<2>(pv, prow, f, ad_shape(pv.n, pv.m, 2), best, bj); break;
+        }
         if (threadIdx.x == 0) {
             a.out_score[p] = best;
             a.out_end[p] = bj;

@@ -203,15 +203,21 @@ def test_antidiag_short_regions_padded_stride(L):
 def test_antidiag_ties_first_column(L):
     """Small-integer queries and levels, so the last row holds the same
     minimum at many columns, within a tile and across tiles and row blocks.
-    The query lengths put row n-1 at every row slot of its thread for 2, 4
-    and 8 rows per thread (the slot below which the kernel's weight-0 rows
-    carry the prefix minimum) and at the last slot (no weight-0 rows).
-    Score bits and first column equal the float oracle's."""
+    The shapes put row n-1 at the last row slot of its thread (no weight-0
+    rows below it) and at an inner slot (weight-0 rows carry its prefix
+    minimum down), on one and on several row blocks, for every rows-per-
+    thread count the kernel's step-count model picks (2 to 8; it gives 2
+    only to single-block pairs).  Regions of 2,049-4,096 levels run at the
+    2,048-level cut-off.  Score bits and first column equal the float
+    oracle's."""
     from oracle import oracle
     rng = np.random.default_rng(12)
     ns = [1, 2, 3, 255, 256, 511, 600, 601, 602, 603, 1023, 1024, 1500, 1501, 1502, 1503, 2047, 2048, 2049,
           2600, 2601, 2602, 2603, 2604, 2605, 2606, 2607, 3072, 4095, 4096, 4097, 5003, 6143, 6144]
     ms = [4097 + int(rng.integers(0, 5000)) for _ in ns]
+    # shapes that complete the cases above (R picked: 5, 5, 7, 7, 4, 4, 5, 7; then 3, 3)
+    ns += [1025, 1026, 1537, 1540, 1793, 1796, 2050, 3073, 1281, 1282]
+    ms += [4097] * 8 + [3300, 3300]
     reads = [rng.integers(0, 3, n).astype(np.float32) for n in ns]
     r = rng.integers(0, 3, sum(ms)).astype(np.float32)
     pairs, off = [], 0
@@ -219,7 +225,8 @@ def test_antidiag_ties_first_column(L):
         pairs.append((i, off, m, False))
         off += m
     b = W._pack("antidiag_ties", reads, pairs, r, {})
-    for kw in (dict(long_kernel=L.LONG_ANTIDIAG), dict(long_kernel=L.LONG_ANTIDIAG, mode=L.MODE_PLAIN)):
+    for kw in (dict(long_kernel=L.LONG_ANTIDIAG), dict(long_kernel=L.LONG_ANTIDIAG, mode=L.MODE_PLAIN),
+               dict(long_kernel=L.LONG_ANTIDIAG, single_max=2048)):
         print(f"  gpu: antidiag ties {kw}", flush=True)
         s, e = _run(L, b, **kw)
         for p in range(b.n_pairs):
