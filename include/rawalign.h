@@ -71,7 +71,8 @@ extern "C" {
 
 /* Kernels for regions longer than one stripe (above opts.single_max levels). */
 #define RAWALIGN_LONG_STRIPED 0     /* one wave sweeps the stripes in turn, edges through device memory */
-#define RAWALIGN_LONG_ANTIDIAG 1    /* one workgroup per pair sweeps anti-diagonals of 256-row blocks through LDS;
+#define RAWALIGN_LONG_ANTIDIAG 1    /* one 256-thread workgroup per pair sweeps anti-diagonals of R x 8 tiles,
+                                       edges through LDS (Sec. 2.4.4);
                                        plain batches only (rawalign_dtw_extend rejects it) */
 #define RAWALIGN_LONG_PIPELINE 2    /* opts.pipe_waves waves share each pair, one stripe each in turn, the
                                        stripes pipelined: a stripe starts as soon as its left neighbour has

@@ -147,7 +147,7 @@ def test_long_regions_multi_stripe(L):
 
 def test_antidiag_kernel_against_oracle(L):
     """The anti-diagonal kernel on its own: queries around its row-block
-    sizes (256 threads x 2, 4 or 8 rows, picked per pair by a step-count
+    sizes (256 threads x 2 to 8 rows, picked per pair by a step-count
     model) and several blocks, regions just above one stripe up to the
     maximum, against the float oracle bit for bit."""
     from oracle import oracle
