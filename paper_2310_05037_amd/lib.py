@@ -159,7 +159,10 @@ def opts_default() -> Opts:
 
 def make_opts(**kw) -> Opts:
     o = opts_default()
+    names = {f for f, _ in Opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise ValueError(f"rawalign_opts has no field {k!r}")
         setattr(o, k, int(v))
     return o
 

@@ -69,6 +69,8 @@ def test_argument_errors_without_device(L):
     o.long_kernel = 7
     rc = so.rawalign_dtw_batch_ex(fake, 10, fake, fake, fake, 10, fake, fake, 2, fake, fake, None, ctypes.byref(o))
     assert rc == L.RAWALIGN_EINVAL and b"long_kernel" in so.rawalign_last_error()
+    with pytest.raises(ValueError):
+        L.make_opts(pipe_wave=4)   # a misspelt field is an error, not a no-op
     # the anti-diagonal kernel runs plain batches only, not the streaming extension
     o = L.opts_default()
     o.long_kernel = L.LONG_ANTIDIAG
