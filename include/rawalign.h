@@ -380,8 +380,10 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
  *              for regions above 2048 levels (not the tuned settings)
  * Pairs of at most 64 levels are aligned one pair per lane (grouped on the
  * device into 8 width classes, longest queries first); wider ones by the
- * striped kernels.  With three streams the width classes and the striped
- * kernels run concurrently on internal streams joined back to `stream`.
+ * striped kernels.  With three streams the call forks before planning: the
+ * width-class planning and the width classes run on internal streams, the
+ * striped routes on `stream` itself, all concurrently, joined back to
+ * `stream` before the call returns its work to it.
  * Degenerate pairs: n == m == 0 (the anchors touch diagonally) costs 0;
  * n == 0 or m == 0 alone costs +inf (no path through the gap's own cells).
  * Invalid slices get NaN (end -2), as in rawalign_dtw_batch.  Scratch as in

@@ -299,47 +299,70 @@ hipError_t launch_span_finish(const int32_t *end, const int32_t *rev_end, int64_
 
 // ---- mapping decision (Sec. 2.3) ----------------------------------------------
 
-__global__ void k_decide(const float *__restrict__ score, int64_t n_pairs, const int64_t *__restrict__ cand_off,
-                         const int32_t *__restrict__ cand_cnt, const int32_t *__restrict__ n_events,
-                         int64_t n_reads, double b_match, double threshold, int32_t *out_best,
-                         double *out_score, uint8_t *out_mapped, bool per_candidate) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_reads) return;
-    const int64_t p0 = cand_off[k];
-    const int cnt = cand_cnt[k];
-    if (cnt < 0 || p0 < 0 || p0 + cnt > n_pairs) {   // candidate range outside the score array
-        out_best[k] = -2;
-        out_score[k] = __builtin_nan("");
-        out_mapped[k] = 0;
-        return;
-    }
-    // Score = B_Match * N_Read - C_DTW; highest wins, smallest index on ties.
-    // Anchored chains count the events each chain aligns.  A NaN cost (the
-    // sentinel of a pair that was not aligned: invalid slice, unsupported
-    // shape) is no candidate at all, so it can neither win nor block a later
-    // candidate.
-    const double bonus = per_candidate ? 0.0 : b_match * (double)n_events[k];
-    int32_t best = -1;
-    double bs = -__builtin_inf();
-    for (int c = 0; c < cnt; ++c) {
-        const float cost = score[p0 + c];
-        if (cost != cost) continue;
-        const double s = (per_candidate ? b_match * (double)n_events[p0 + c] : bonus) - (double)cost;
-        if (best < 0 || s > bs) {
-            best = (int32_t)(p0 + c);
-            bs = s;
+// One wave per read.  Score = B_Match * N_Read - C_DTW; the highest wins,
+// the smallest candidate index on ties.  Anchored chains count the events
+// each chain aligns.  A NaN cost (the sentinel of a pair that was not
+// aligned: invalid slice, unsupported shape) is no candidate at all, so it
+// can neither win nor block a later candidate.  Lane l scans candidates l,
+// l + 64, ... in order and keeps its first highest; the wave then keeps the
+// highest score and, among equal scores, the smallest index.  With B_Match
+// finite (checked by every entry point) no score is NaN, so this is the
+// candidate a sequential first-highest scan picks.
+__global__ __launch_bounds__(256) void k_decide(const float *__restrict__ score, int64_t n_pairs,
+                                                const int64_t *__restrict__ cand_off,
+                                                const int32_t *__restrict__ cand_cnt,
+                                                const int32_t *__restrict__ n_events, int64_t n_reads,
+                                                double b_match, double threshold, int32_t *out_best,
+                                                double *out_score, uint8_t *out_mapped, bool per_candidate) {
+    const int lane = __lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; k < n_reads; k += waves) {
+        const int64_t p0 = cand_off[k];   // wave-uniform from here on
+        const int cnt = cand_cnt[k];
+        if (cnt < 0 || p0 < 0 || p0 + cnt > n_pairs) {   // candidate range outside the score array
+            if (lane == 0) {
+                out_best[k] = -2;
+                out_score[k] = __builtin_nan("");
+                out_mapped[k] = 0;
+            }
+            continue;
+        }
+        const double bonus = per_candidate ? 0.0 : b_match * (double)n_events[k];
+        int32_t best = -1;
+        double bs = -__builtin_inf();
+        for (int c = lane; c < cnt; c += 64) {
+            const float cost = score[p0 + c];
+            if (cost != cost) continue;
+            const double s = (per_candidate ? b_match * (double)n_events[p0 + c] : bonus) - (double)cost;
+            if (best < 0 || s > bs) {
+                best = (int32_t)(p0 + c);
+                bs = s;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double os = __shfl_xor(bs, off, 64);
+            const int32_t ob = __shfl_xor(best, off, 64);
+            if (ob >= 0 && (best < 0 || os > bs || (os == bs && ob < best))) {
+                best = ob;
+                bs = os;
+            }
+        }
+        if (lane == 0) {
+            out_best[k] = best;
+            out_score[k] = bs;
+            out_mapped[k] = (best >= 0 && bs >= threshold) ? 1 : 0;
         }
     }
-    out_best[k] = best;
-    out_score[k] = bs;
-    out_mapped[k] = (best >= 0 && bs >= threshold) ? 1 : 0;
 }
 
 hipError_t launch_decide(const float *score, int64_t n_pairs, const int64_t *cand_off, const int32_t *cand_cnt,
                          const int32_t *n_events, int64_t n_reads, double b_match, double threshold,
                          int32_t *out_best, double *out_score, uint8_t *out_mapped, bool per_candidate,
                          hipStream_t stream) {
-    const unsigned g = (unsigned)((n_reads + 255) / 256);
+    // four waves (one read each at a time) per workgroup
+    const int64_t g64 = (n_reads + 3) / 4;
+    const unsigned g = (unsigned)(g64 < (1 << 20) ? g64 : (1 << 20));
     hipLaunchKernelGGL(k_decide, dim3(g), dim3(256), 0, stream, score, n_pairs, cand_off, cand_cnt, n_events,
                        n_reads, b_match, threshold, out_best, out_score, out_mapped, per_candidate);
     return hipGetLastError();

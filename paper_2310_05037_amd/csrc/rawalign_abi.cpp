@@ -59,6 +59,7 @@ struct StreamScratch {
     int64_t tiny_capacity = 0;
     hipStream_t sub[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr;
+    hipEvent_t gap_planned = nullptr;   // global calls: the gap plan on sub[0] is done
     hipEvent_t join[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev[8] = {};      // timing: plan start/end, then start/end of lo, hi, long
 };
@@ -170,6 +171,8 @@ int get_scratch(int dev, hipStream_t stream, int64_t n_pairs, int64_t edge_slots
             if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
         }
         e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        e = hipEventCreateWithFlags(&s.gap_planned, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
     if (timing && !s.ev[0]) {
@@ -402,27 +405,45 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
         if (rc) return rc;
     }
 
+    // Global calls on three streams fork before planning: the gap plan runs
+    // on sub[0] beside the main plan, the width classes then go round the
+    // three sub-streams, and the striped routes follow the main plan on the
+    // caller's stream, so four queues work at once. The two plans touch
+    // disjoint pairs (the main plan skips every gap the one-lane kernel takes)
+    // and separate scratch.
+    const bool split = tiny && concurrent;
     hipError_t e;
-    if (timing && (e = hipEventRecord(s->ev[0], c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
-    if (e != hipSuccess) return hip_fail(e, "plan kernels");
-    if (tiny) {
-        e = ra::launch_tiny_plan(a, c.n_pairs, tiny_view(*s), c.stream);
-        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane planning");
-    }
-    if (timing) (void)hipEventRecord(s->ev[1], c.stream);
     hipStream_t st[3] = {c.stream, c.stream, c.stream};
-    if (concurrent) {   // never with noalloc (checked above)
+    auto fork = [&]() -> int {   // never with noalloc (checked above)
         if ((e = hipEventRecord(s->fork, c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
         for (int i = 0; i < 3; ++i) {
             st[i] = s->sub[i];
             if ((e = hipStreamWaitEvent(st[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
         }
+        return RAWALIGN_OK;
+    };
+    if (timing && (e = hipEventRecord(s->ev[0], c.stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (split && (rc = fork()) != RAWALIGN_OK) return rc;
+    e = ra::launch_plan(a, c.n_pairs, cfg, ps, c.stream);
+    if (e != hipSuccess) return hip_fail(e, "plan kernels");
+    if (tiny) {
+        e = ra::launch_tiny_plan(a, c.n_pairs, tiny_view(*s), st[0]);
+        if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane planning");
+    }
+    if (timing) (void)hipEventRecord(s->ev[1], c.stream);   // split: the main plan only
+    if (split) {
+        if ((e = hipEventRecord(s->gap_planned, st[0])) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        for (int i = 1; i < 3; ++i)
+            if ((e = hipStreamWaitEvent(st[i], s->gap_planned, 0)) != hipSuccess)
+                return hip_fail(e, "hipStreamWaitEvent");
+    } else if (concurrent && (rc = fork()) != RAWALIGN_OK) {
+        return rc;
     }
     if (tiny) {
         e = ra::launch_tiny(a, c.n_pairs, tiny_view(*s), info.cus, st);
         if (e != hipSuccess) return hip_fail(e, "one-pair-per-lane kernels");
     }
+    const hipStream_t route_st[3] = {split ? c.stream : st[0], split ? c.stream : st[1], split ? c.stream : st[2]};
     // Longest regions first: they bound the makespan.
     const char *names[3] = {antidiag ? "anti-diagonal kernel" : pipeline ? "pipelined multi-stripe kernel"
                                                                          : "multi-stripe kernel",
@@ -430,17 +451,18 @@ int run(const Call &c, const rawalign_opts &o, bool noalloc = false) {
                             "single-stripe kernel (2-32 columns per lane)"};
     const int ev_slot[3] = {6, 4, 2};   // long, hi, lo
     for (int i = 0; i < 3; ++i) {
-        if (timing) (void)hipEventRecord(s->ev[ev_slot[i]], st[i]);
+        const hipStream_t rs = route_st[i];
+        if (timing) (void)hipEventRecord(s->ev[ev_slot[i]], rs);
         if (i == 0)
-            e = antidiag ? ra::launch_antidiag(a, c.n_pairs, cfg, ps, st[i])
-                : pipeline ? ra::launch_pipe(pipe_waves, a, c.n_pairs, cfg, ps, st[i])
-                           : ra::launch_multi(a, c.n_pairs, cfg, ps, st[i]);
+            e = antidiag ? ra::launch_antidiag(a, c.n_pairs, cfg, ps, rs)
+                : pipeline ? ra::launch_pipe(pipe_waves, a, c.n_pairs, cfg, ps, rs)
+                           : ra::launch_multi(a, c.n_pairs, cfg, ps, rs);
         else if (i == 1)
-            e = ra::launch_single_hi(a, c.n_pairs, cfg, ps, st[i]);
+            e = ra::launch_single_hi(a, c.n_pairs, cfg, ps, rs);
         else
-            e = ra::launch_single_lo(a, c.n_pairs, cfg, ps, st[i]);
+            e = ra::launch_single_lo(a, c.n_pairs, cfg, ps, rs);
         if (e != hipSuccess) return hip_fail(e, names[i]);
-        if (timing) (void)hipEventRecord(s->ev[ev_slot[i] + 1], st[i]);
+        if (timing) (void)hipEventRecord(s->ev[ev_slot[i] + 1], rs);
     }
     if (concurrent) {
         for (int i = 0; i < 3; ++i) {

@@ -349,6 +349,52 @@ def test_decide_matches_oracle(L):
         assert np.array_equal(om.cpu().numpy(), rm)
 
 
+def test_decide_ties_and_many_candidates(L):
+    """The decision of a read spread over a wave's lanes: costs drawn from a
+    few values, so that equal best scores fall on candidates of different
+    lanes and of the same lane, NaN sentinels and +inf costs among them, and
+    reads of 0 to 300 candidates (one and several candidates per lane).  The
+    best index, score and flag equal the oracle's first-highest scan."""
+    import torch
+    from oracle import oracle
+    rng = np.random.default_rng(41)
+    counts = np.array([0, 1, 2, 63, 64, 65, 127, 128, 129, 200, 300, 5, 64, 130] * 6, dtype=np.int32)
+    n_reads = len(counts)
+    cand_off = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    n_pairs = int(counts.sum())
+    cost = rng.choice(np.array([0.5, 1.0, 2.0, 3.0, np.inf, np.nan], dtype=np.float32), size=n_pairs,
+                      p=[0.1, 0.2, 0.3, 0.2, 0.1, 0.1]).astype(np.float32)
+    # reads whose candidates are all +inf, all NaN, or tie at one value everywhere
+    for k, v in ((1, np.inf), (2, np.nan), (3, 2.0), (4, 1.0)):
+        cost[cand_off[k]:cand_off[k] + counts[k]] = v
+    n_events = rng.integers(0, 120, size=n_reads).astype(np.int32)
+    dev = "cuda"
+    ob = torch.empty(n_reads, dtype=torch.int32, device=dev)
+    os_ = torch.empty(n_reads, dtype=torch.float64, device=dev)
+    om = torch.empty(n_reads, dtype=torch.uint8, device=dev)
+    for bm, th in ((0.4, 20.0), (0.0, 0.0), (0.3, -1.0)):
+        _say(f"  gpu: decide ties reads={n_reads} pairs={n_pairs} b_match={bm}")
+        L.rawalign_decide(torch.from_numpy(cost).to(dev), torch.from_numpy(cand_off).to(dev),
+                          torch.from_numpy(counts).to(dev), torch.from_numpy(n_events).to(dev),
+                          ob, os_, om, b_match=bm, threshold=th)
+        torch.cuda.synchronize()
+        rb, rs, rm = oracle.decide(cost, cand_off, counts, n_events, bm, th)
+        assert np.array_equal(ob.cpu().numpy(), rb)
+        assert np.array_equal(os_.cpu().numpy().view(np.uint64), rs.view(np.uint64))
+        assert np.array_equal(om.cpu().numpy(), rm)
+    # the ties really occur: several reads have more than one best candidate
+    # in different lanes (indices 64 or more apart)
+    multi = 0
+    for k in range(n_reads):
+        c = cost[cand_off[k]:cand_off[k] + counts[k]].astype(np.float64)
+        ok = ~np.isnan(c)
+        if ok.sum() < 2:
+            continue
+        best = np.flatnonzero(ok & (c == np.nanmin(c)))
+        multi += int(best.max() - best.min() >= 64)
+    assert multi >= 10
+
+
 def test_autotune_and_tuning_cache(L, tmp_path):
     """The autotuner picks a valid setting, writes it to a cache that loads
     back to the same setting, and the tuned path (opts NULL) gives the same
