@@ -24,7 +24,7 @@
 namespace ra {
 
 constexpr int kTinyBins = kTinyClasses * kTinyBuckets;   // 1024
-constexpr int kTinyPlanBlock = 256;
+constexpr int kTinyPlanBlock = 1024;   // a few pairs per thread, as in the main planner
 
 RA_DEV int tiny_class(int m) {
     int c = 0;

@@ -140,7 +140,10 @@ __global__ void k_plan_zero(PlanScratch s) {
     }
 }
 
-constexpr int kPlanBlock = 256;
+// 1024 threads: each thread classifies a few pairs of a million-pair batch,
+// one after another; at 256 threads that chain of dependent loads set the
+// planning time.
+constexpr int kPlanBlock = 1024;
 constexpr int kBins = kNumRoutes * kBuckets;
 // Workgroups take contiguous ranges of pairs; at most kPlanGrid of them, so
 // a batch of millions of pairs still adds each busy bin to the global
