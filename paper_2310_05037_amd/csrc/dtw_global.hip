@@ -17,7 +17,9 @@
 //     |x| modifier, with no cross-lane traffic at all;
 //   * the lanes of a wave take gaps of one width class with similar query
 //     lengths (planned on the device: width class, then quarter octaves of
-//     n, longest first), so little of a wave idles.
+//     n, longest first), so little of a wave idles;
+//   * the two widest classes (W = 48, 64) take two lanes per gap, one per
+//     half of the slots, the second a row behind (k_tiny_pair).
 // Gaps wider than 64 levels go to the striped kernels in global mode.
 #include "dtw_device.h"
 
@@ -198,12 +200,111 @@ void k_tiny(PairArrays a, TinyScratch t, int cls) {
     }
 }
 
+// The two widest classes take two lanes per gap.  Alone, a lane's longest
+// gap sets such a class's time: one instruction chain of n x W cells (W = 64,
+// n = 283 on the anchored workload).  Lane 2k holds slots [0, W/2) of gap k
+// and lane 2k+1 slots [W/2, W); the second runs one row behind and takes the
+// west value of its first slot from its partner's last slot of that row (one
+// DPP move per row), its north-west value from the row before.  Each chain
+// is half as long, with half the registers.  The corner of row -1 lies in
+// the first half (the class's regions are wider than W/2 + pad), so the
+// second lane's row -1 is all +inf: its first step, on a row before the
+// gap, leaves it at +inf, and no step needs to be peeled off.
+template <int H>
+RA_DEV void tiny_half_row(float qv, float nw0, float w0, const float (&rv)[H], const float (&Ao)[H],
+                          float (&An)[H]) {
+    An[0] = cell(qv, rv[0], nw0, Ao[0], w0);
+#pragma unroll
+    for (int v = 1; v < H; ++v) An[v] = cell(qv, rv[v], Ao[v - 1], Ao[v], An[v - 1]);
+}
+
+// Rows i0 - half .. i0 - half + kTinyQB - 1 of the lane, clamped to [0, n).
+RA_DEV void tiny_qblock_half(const float *qp, int n, int i0, float (&qb)[kTinyQB]) {
+#pragma unroll
+    for (int k = 0; k < kTinyQB; ++k) {
+        const int i = i0 + k;
+        qb[k] = qp[i < 0 ? 0 : (i < n ? i : n - 1)];
+    }
+}
+
+RA_DEV float partner(float x) {   // lane 2k+1 receives lane 2k's value (and 2k receives 2k+1's)
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_tiny_pair(PairArrays a, TinyScratch t, int cls) {
+    constexpr int H = W / 2;
+    const int count = t.counts[cls];
+    const int32_t *list = t.list + t.base[cls];
+    const int lane = __lane_id();
+    const int half = lane & 1;
+    for (int base = blockIdx.x * 32; base < count; base += gridDim.x * 32) {
+        const int g = base + (lane >> 1);
+        const bool act = g < count;
+        const int p = list[act ? g : count - 1];   // idle pairs of lanes repeat the last gap
+        const int n = a.q_len[p];                  // >= 1
+        const int m = a.r_len[p];                  // W/2 + pad < m <= W
+        const float *qp = a.q + a.q_off[p];
+        const float *rs = a.r + a.r_off[p] - (W - m);
+        const int pad = W - m;
+        const int v0 = half * H;
+        float rv[H], A[H], B[H];
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+            rv[v] = v0 + v >= pad ? rs[v0 + v] : kInf;
+            A[v] = v0 + v == pad - 1 ? 0.0f : kInf;
+        }
+        float corner = half == 0 && pad == 0 ? 0.0f : kInf;
+        int nmax = n;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
+        float res = kInf;
+        float mylast = kInf;      // this lane's last slot, previous step
+        float edge_prev = kInf;   // the partner's last slot two steps back
+        float qc[kTinyQB], qn[kTinyQB];
+        tiny_qblock_half(qp, n, -half, qc);
+        // step s: the first lane computes row s, the second row s - 1
+        for (int i0 = 0; i0 <= nmax; i0 += kTinyQB) {
+            tiny_qblock_half(qp, n, i0 + kTinyQB - half, qn);
+#pragma unroll
+            for (int k = 0; k < kTinyQB; k += 2) {
+                float edge = partner(mylast);
+                tiny_half_row<H>(qc[k], half ? edge_prev : corner, half ? edge : kInf, rv, A, B);
+                corner = kInf;
+                edge_prev = edge;
+                mylast = B[H - 1];
+                if (half && i0 + k == n) res = B[H - 1];
+                edge = partner(mylast);
+                tiny_half_row<H>(qc[k + 1], half ? edge_prev : kInf, half ? edge : kInf, rv, B, A);
+                edge_prev = edge;
+                mylast = A[H - 1];
+                if (half && i0 + k + 1 == n) res = A[H - 1];
+            }
+#pragma unroll
+            for (int k = 0; k < kTinyQB; ++k) qc[k] = qn[k];
+        }
+        if (act && half) {
+            a.out_score[p] = res;
+            if (a.out_end) a.out_end[p] = m - 1;
+        }
+    }
+}
+
+// Classes that take two lanes per gap (their regions are wider than half the
+// class width plus the largest pad, so the corner stays in the first half).
+RA_HOST_DEV constexpr bool tiny_paired(int c) { return c >= 6; }
+static_assert(tiny_width(5) >= tiny_width(6) / 2 && tiny_width(6) >= tiny_width(7) / 2,
+              "paired classes need the corner of row -1 in the first lane's half");
+
 template <int C>
 static int tiny_occupancy() {
     static int occ = 0;
     if (!occ) {
         int nb = 0;
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiny<tiny_width(C)>, 64, 0);
+        if constexpr (tiny_paired(C))
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiny_pair<tiny_width(C)>, 64, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiny<tiny_width(C)>, 64, 0);
         occ = nb > 0 ? nb : 1;
     }
     return occ;
@@ -214,11 +315,17 @@ template <int C>
 static hipError_t launch_tiny_class(const PairArrays &a, int64_t n_pairs, const TinyScratch &t, int cus,
                                     const hipStream_t *st) {
     if constexpr (C >= 0) {
-        // no more waves than 64 pairs each could need
-        const int64_t need = (n_pairs + 63) / 64;
+        // no more waves than the pairs could need (64 gaps per wave, 32 when paired)
+        const int per = tiny_paired(C) ? 32 : 64;
+        const int64_t need = (n_pairs + per - 1) / per;
         const int64_t full = (int64_t)cus * tiny_occupancy<C>();
         const unsigned grid = (unsigned)(need < full ? need : full);
-        hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[(kTinyClasses - 1 - C) % 3], a, t, C);
+        if constexpr (tiny_paired(C))
+            hipLaunchKernelGGL(k_tiny_pair<tiny_width(C)>, dim3(grid), dim3(64), 0, st[(kTinyClasses - 1 - C) % 3],
+                               a, t, C);
+        else
+            hipLaunchKernelGGL(k_tiny<tiny_width(C)>, dim3(grid), dim3(64), 0, st[(kTinyClasses - 1 - C) % 3], a,
+                               t, C);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_tiny_class<C - 1>(a, n_pairs, t, cus, st);
