@@ -18,8 +18,8 @@
 //   * the lanes of a wave take gaps of one width class with similar query
 //     lengths (planned on the device: width class, then quarter octaves of
 //     n, longest first), so little of a wave idles;
-//   * the two widest classes (W = 48, 64) take two lanes per gap, one per
-//     half of the slots, the second a row behind (k_tiny_pair).
+//   * the four widest classes (W = 24 .. 64) take two lanes per gap, one
+//     per half of the slots, the second a row behind (k_tiny_pair).
 // Gaps wider than 64 levels go to the striped kernels in global mode.
 #include "dtw_device.h"
 
@@ -200,16 +200,17 @@ void k_tiny(PairArrays a, TinyScratch t, int cls) {
     }
 }
 
-// The two widest classes take two lanes per gap.  Alone, a lane's longest
-// gap sets such a class's time: one instruction chain of n x W cells (W = 64,
-// n = 283 on the anchored workload).  Lane 2k holds slots [0, W/2) of gap k
-// and lane 2k+1 slots [W/2, W); the second runs one row behind and takes the
-// west value of its first slot from its partner's last slot of that row (one
-// DPP move per row), its north-west value from the row before.  Each chain
-// is half as long, with half the registers.  The corner of row -1 lies in
-// the first half (the class's regions are wider than W/2 + pad), so the
-// second lane's row -1 is all +inf: its first step, on a row before the
-// gap, leaves it at +inf, and no step needs to be peeled off.
+// The four widest classes (W = 24 .. 64) take two lanes per gap.  Alone, a
+// lane's longest gap sets such a class's time: one instruction chain of
+// n x W cells (W = 64, n = 283 on the anchored workload).  Lane 2k holds
+// slots [0, W/2) of gap k and lane 2k+1 slots [W/2, W); the second runs one
+// row behind and takes the west value of its first slot from its partner's
+// last slot of that row (one DPP move per row), its north-west value from
+// the row before.  Each chain is half as long, with fewer registers.  Every
+// region of these classes has more than W/2 levels, so the pad W - m is
+// below W/2 and the corner of row -1 (slot pad - 1) lies in the first half;
+// the second lane's row -1 is then all +inf, its first step (on a row
+// before the gap) leaves it at +inf, and no step needs to be peeled off.
 template <int H>
 RA_DEV void tiny_half_row(float qv, float nw0, float w0, const float (&rv)[H], const float (&Ao)[H],
                           float (&An)[H]) {
@@ -290,10 +291,13 @@ __global__ __launch_bounds__(64) void k_tiny_pair(PairArrays a, TinyScratch t, i
     }
 }
 
-// Classes that take two lanes per gap (their regions are wider than half the
-// class width plus the largest pad, so the corner stays in the first half).
-RA_HOST_DEV constexpr bool tiny_paired(int c) { return c >= 6; }
-static_assert(tiny_width(5) >= tiny_width(6) / 2 && tiny_width(6) >= tiny_width(7) / 2,
+// Classes that take two lanes per gap: every region of such a class is
+// wider than the class below it, and that class is at least half as wide,
+// so the pad is below W/2 and the corner stays in the first half.  Pairing
+// the narrower classes too (down to W = 8) measured the same.
+RA_HOST_DEV constexpr bool tiny_paired(int c) { return c >= 4; }
+static_assert(tiny_width(3) >= tiny_width(4) / 2 && tiny_width(4) >= tiny_width(5) / 2 &&
+                  tiny_width(5) >= tiny_width(6) / 2 && tiny_width(6) >= tiny_width(7) / 2,
               "paired classes need the corner of row -1 in the first lane's half");
 
 template <int C>
