@@ -387,7 +387,8 @@ int rawalign_dtw_band(const float *q, int64_t q_size, const int64_t *q_off, cons
  * Degenerate pairs: n == m == 0 (the anchors touch diagonally) costs 0;
  * n == 0 or m == 0 alone costs +inf (no path through the gap's own cells).
  * Invalid slices get NaN (end -2), as in rawalign_dtw_batch.  Scratch as in
- * rawalign_dtw_batch, plus 4 bytes per pair for the per-lane planning.
+ * rawalign_dtw_batch, plus 32 bytes per pair for the per-lane planning (one
+ * record per gap).
  */
 int rawalign_dtw_global_batch(const float *q, int64_t q_size, const int64_t *q_off, const int32_t *q_len,
                               const float *r, int64_t r_size, const int64_t *r_off, const int32_t *r_len,

@@ -120,7 +120,14 @@ __global__ __launch_bounds__(kTinyPlanBlock) void k_tiny_scatter(PairArrays a, i
     for (int64_t p = lo + threadIdx.x; p < hi; p += kTinyPlanBlock) {
         if (tiny_pair(a, p)) {
             const int bin = tiny_bin(a.q_len[p], a.r_len[p]);
-            t.list[base[bin] + atomicAdd(&cnt[bin], 1)] = (int32_t)p;
+            TinyRec rc;
+            rc.q_off = a.q_off[p];
+            rc.r_off = a.r_off[p];
+            rc.p = (int32_t)p;
+            rc.n = a.q_len[p];
+            rc.m = a.r_len[p];
+            rc.unused = 0;
+            t.list[base[bin] + atomicAdd(&cnt[bin], 1)] = rc;
         }
     }
 }
@@ -145,24 +152,25 @@ RA_DEV void tiny_qblock(const float *qp, int n, int i0, float (&qb)[kTinyQB]) {
 }
 
 // Gaps of width class `cls` (m <= W levels), 64 per wave, in list order.
-// Narrow classes are bound by the latency of their gathers (gap list, then
-// lengths and offsets, then levels and events), not by their few cells.
-// W = 12 and 16 ask the compiler for 6 resident waves per SIMD instead of 5
-// (at most 80 VGPRs, no spills), which shortens them by about 12%; the same
-// request for 8 waves at W <= 8 or 5 at W = 24 made those slower.
+// Narrow classes are bound by the latency of their gathers (the gap record,
+// then levels and events), not by their few cells.  W = 12 asks the
+// compiler for 6 resident waves per SIMD instead of 5 (at most 80 VGPRs, no
+// spills); W = 16 would spill there.  The same request for 8 waves at W <= 8
+// made those classes slower.
 template <int W>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 12 || W == 16 ? 6 : 1)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(W == 12 ? 6 : 1)))
 void k_tiny(PairArrays a, TinyScratch t, int cls) {
     const int count = t.counts[cls];
-    const int32_t *list = t.list + t.base[cls];
+    const TinyRec *list = t.list + t.base[cls];
     const int lane = __lane_id();
     for (int base = blockIdx.x * 64; base < count; base += gridDim.x * 64) {
         const bool act = base + lane < count;
-        const int p = list[act ? base + lane : count - 1];   // idle lanes repeat the last gap
-        const int n = a.q_len[p];                            // >= 1
-        const int m = a.r_len[p];                            // 1 .. W
-        const float *qp = a.q + a.q_off[p];
-        const float *rp = a.r + a.r_off[p];
+        const TinyRec rc = list[act ? base + lane : count - 1];   // idle lanes repeat the last gap
+        const int p = rc.p;
+        const int n = rc.n;   // >= 1
+        const int m = rc.m;   // 1 .. W
+        const float *qp = a.q + rc.q_off;
+        const float *rp = a.r + rc.r_off;
         const int pad = W - m;
         // Slot v holds level v - pad; slots left of the gap are never read
         // from memory (the load is masked off for them).
@@ -236,17 +244,18 @@ template <int W>
 __global__ __launch_bounds__(64) void k_tiny_pair(PairArrays a, TinyScratch t, int cls) {
     constexpr int H = W / 2;
     const int count = t.counts[cls];
-    const int32_t *list = t.list + t.base[cls];
+    const TinyRec *list = t.list + t.base[cls];
     const int lane = __lane_id();
     const int half = lane & 1;
     for (int base = blockIdx.x * 32; base < count; base += gridDim.x * 32) {
         const int g = base + (lane >> 1);
         const bool act = g < count;
-        const int p = list[act ? g : count - 1];   // idle pairs of lanes repeat the last gap
-        const int n = a.q_len[p];                  // >= 1
-        const int m = a.r_len[p];                  // W/2 + pad < m <= W
-        const float *qp = a.q + a.q_off[p];
-        const float *rs = a.r + a.r_off[p] - (W - m);
+        const TinyRec rc = list[act ? g : count - 1];   // idle pairs of lanes repeat the last gap
+        const int p = rc.p;
+        const int n = rc.n;   // >= 1
+        const int m = rc.m;   // W/2 < m <= W
+        const float *qp = a.q + rc.q_off;
+        const float *rs = a.r + rc.r_off - (W - m);
         const int pad = W - m;
         const int v0 = half * H;
         float rv[H], A[H], B[H];

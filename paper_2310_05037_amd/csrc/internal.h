@@ -112,11 +112,23 @@ RA_HOST_DEV constexpr int tiny_width(int c) {
     return c == 0 ? 4 : c == 1 ? 8 : c == 2 ? 12 : c == 3 ? 16 : c == 4 ? 24 : c == 5 ? 32 : c == 6 ? 48 : 64;
 }
 
+// One gap of the one-lane kernel's list: its pair index and what the kernel
+// reads of it, so a lane starts with one coalesced 32-byte load instead of
+// a list entry and then four gathers that depend on it.
+struct alignas(16) TinyRec {
+    int64_t q_off;
+    int64_t r_off;
+    int32_t p;
+    int32_t n;
+    int32_t m;
+    int32_t unused;
+};
+
 struct TinyScratch {
     int32_t *hist;      // [kTinyClasses * kTinyBuckets] histogram, then cursors
     int32_t *counts;    // [kTinyClasses] pairs per width class
     int32_t *base;      // [kTinyClasses] first list slot of each class
-    int32_t *list;      // [capacity] pair indices, class by class, longest queries first
+    TinyRec *list;      // [capacity] gaps, class by class, longest queries first
     int64_t capacity;
 };
 

@@ -55,7 +55,7 @@ struct StreamScratch {
     float *rowbuf = nullptr;    // anti-diagonal kernel only
     int64_t row_slots = 0;
     int32_t *tiny_words = nullptr;   // one-pair-per-lane planning: hist | counts | base
-    int32_t *tiny_list = nullptr;
+    ra::TinyRec *tiny_list = nullptr;
     int64_t tiny_capacity = 0;
     hipStream_t sub[3] = {nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr;
@@ -203,7 +203,7 @@ int get_tiny(StreamScratch &s, int64_t n_pairs) {
         if (s.tiny_list) (void)hipFree(s.tiny_list);
         s.tiny_list = nullptr;
         s.tiny_capacity = 0;
-        e = hipMalloc((void **)&s.tiny_list, (size_t)cap * sizeof(int32_t));
+        e = hipMalloc((void **)&s.tiny_list, (size_t)cap * sizeof(ra::TinyRec));
         if (e != hipSuccess) {
             s.tiny_list = nullptr;
             return alloc_fail(e);
