@@ -713,6 +713,8 @@ def main():
                     help="run only the 4,096-pair plain batch and long-stress legs (library defaults) and print them")
     ap.add_argument("--only-anchored", action="store_true",
                     help="run only the anchor-guided alignment leg and print its JSON (for profiling runs)")
+    ap.add_argument("--only-early-termination", action="store_true",
+                    help="run only the early-termination leg (library defaults, 512-row blocks) and print its JSON")
     ap.add_argument("--opts", type=str, default="", help="JSON dict of rawalign_opts fields for the tuned path")
     ap.add_argument("--no-autotune", action="store_true", help="time the library defaults instead of tuned settings")
     ap.add_argument("--serving-reads", type=int, default=20000, help="reads in the serving leg (0: skip it)")
@@ -753,6 +755,10 @@ def main():
         return
     if args.only_single_read:
         print(json.dumps({"single_read": single_read_leg(lib)}), flush=True)
+        return
+    if args.only_early_termination:
+        print(json.dumps({"early_termination": bnb_leg(lib, workloads.uneven_batch(), lib.make_opts(),
+                                                       steps=args.steps)}), flush=True)
         return
     if args.only_path:
         print(json.dumps({"path": path_leg(lib, workloads.uneven_batch(), None, steps=args.steps)}), flush=True)
