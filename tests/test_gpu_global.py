@@ -89,9 +89,9 @@ def test_global_every_width_class_and_route(L, seed):
 
 
 def test_global_modes_and_degenerate_pairs(L):
-    """Plain and persistent scheduling, one and three streams give the same
-    bits; empty gaps give 0 (both sides) or +inf (one side); invalid slices
-    give NaN, -2."""
+    """Plain and persistent scheduling, one and three streams (with and
+    without timing events) give the same bits; empty gaps give 0 (both
+    sides) or +inf (one side); invalid slices give NaN, -2."""
     rng = np.random.default_rng(7)
     b = W.random_pairs(rng, 400, (0, 90), (0, 120))
     q_len, r_len = b.q_len.copy(), b.r_len.copy()
@@ -109,8 +109,11 @@ def test_global_modes_and_degenerate_pairs(L):
     sub = b.subset(np.flatnonzero(ok))
     s32, s64 = _oracle_global(sub)
     results = []
-    for kw in ({}, {"mode": L.MODE_PLAIN}, {"streams": 3}):
+    for kw in ({}, {"mode": L.MODE_PLAIN}, {"streams": 3}, {"streams": 3, "flags": L.FLAG_TIMING}):
         s, e = _gpu_global(L, b, opts=L.make_opts(**kw))
+        if kw.get("flags"):   # timing on three streams: the plans run side by side, events stay valid
+            t = L.rawalign_last_timing().as_dict()
+            assert all(math.isfinite(v) and v >= 0.0 for v in t.values()), t
         assert math.isnan(s[4]) and e[4] == -2
         for p in range(4):     # (0, 0) -> 0; one side empty -> +inf; end -1
             exp = 0.0 if b.q_len[p] == 0 and b.r_len[p] == 0 else np.inf
