@@ -15,7 +15,7 @@
 //     written by stripe s - 1, read by stripe s, then rewritten by stripe s,
 //     always in that order because stripe s reads row i only after stripe
 //     s - 1 published it and rewrites it only after reading it;
-//   * progress: every kPipeBlock steps a stripe publishes how many edge rows
+//   * progress: every block of steps a stripe publishes how many edge rows
 //     it has stored (release, then an LDS store), and a stripe about to load
 //     edge rows waits until its left neighbour has published them (LDS load,
 //     then acquire);
@@ -33,7 +33,15 @@
 
 namespace ra {
 
-constexpr int kPipeBlock = 64;
+// Steps between progress publications.  A stripe can start once its left
+// neighbour has published a block of rows past the 64-step skew, so each
+// stripe trails the one before by about 64 + 2 blocks of rows.  The
+// streaming extension sweeps 400-row chunks, where that lag over up to 8
+// stripes is most of a chunk's sweep: it publishes every 16 steps.  Plain
+// batches sweep whole queries of thousands of rows and keep 64, where each
+// publication's fence and spin cost more than the shorter lag saves.
+template <bool EXT>
+constexpr int pipe_block() { return EXT ? 16 : 64; }
 constexpr uint64_t kPipeSpinTicks = 500000000ull;   // 5 s
 constexpr int kPipeMaxStripes = kMaxRegion / 2048;   // 32: stripes are at most 2048 columns wide
 static_assert(256 * kMultiMaxK <= 2048, "the pipeline's stripe arrays assume stripes of at most 2048 columns");
@@ -73,9 +81,10 @@ RA_DEV bool spin_until(int32_t *p, int target) {
     }
 }
 
+template <int B>
 struct PipeSync {
     static constexpr bool kActive = true;
-    static constexpr int kBlock = kPipeBlock;
+    static constexpr int kBlock = B;
     PipeShared *sh;
     int s;   // this stripe
 
@@ -98,12 +107,13 @@ struct PipeSync {
 
 template <int C, bool EXT>
 RA_DEV void pipe_stripe(const PairView &pv, int s, float *edge, PipeShared *sh, float &b, int &j) {
-    PipeSync sync{sh, s};
+    using Sync = PipeSync<pipe_block<EXT>()>;
+    Sync sync{sh, s};
     float nc;
     if (s == 0)
-        sweep<C, EXT, false, true, false, PipeSync>(pv, 0, edge, 0.0f, nc, b, j, &sync);
+        sweep<C, EXT, false, true, false, Sync>(pv, 0, edge, 0.0f, nc, b, j, &sync);
     else
-        sweep<C, EXT, true, true, false, PipeSync>(pv, s * 64 * C, edge, 0.0f, nc, b, j, &sync);
+        sweep<C, EXT, true, true, false, Sync>(pv, s * 64 * C, edge, 0.0f, nc, b, j, &sync);
 }
 
 // Columns per lane C = step * H for every H the multi-stripe shapes use.

@@ -4,7 +4,7 @@
 Each wave of a workgroup is a generator that performs, in program order,
 the kernel's shared-memory operations: the epoch wait and the pair index,
 per stripe the progress waits before edge loads, the edge loads and stores
-of lanes 0 and 63 row by row, the progress publications every 64 steps,
+of lanes 0 and 63 row by row, the progress publications every block of steps,
 the corner hand-over, the partial minimum, the finished counter, and the
 last wave's combine, reset and release of the next pair.  A scheduler runs
 the waves in random interleavings (a wave blocked on a wait is not
@@ -13,14 +13,14 @@ that each edge row a stripe loads was written by its left neighbour for
 this pair and not yet overwritten, that every pair's result is written
 exactly once after all its waves are done, and that the counters start at
 zero for every pair.  No DTW arithmetic is modelled: this is the protocol
-only, for the workgroup sizes, block length and pair shapes the kernel
-takes.
+only, for the workgroup sizes, block lengths (16 steps in the streaming
+extension, 64 in plain batches) and pair shapes the kernel takes.
 """
 import random
 
 import pytest
 
-BLOCK = 64           # kPipeBlock
+BLOCKS = (16, 64)    # steps between progress publications: streaming extension, plain batches
 SKEW = 64            # lane 63 finishes row t - 63 at step t
 
 
@@ -36,8 +36,9 @@ class Shared:
 
 
 class Model:
-    def __init__(self, pairs, W, persistent, grid, rng):
+    def __init__(self, pairs, W, persistent, grid, rng, block=64):
         self.pairs = pairs                     # list of (n, S)
+        self.block = block
         self.W = W
         self.persistent = persistent
         self.grid = grid
@@ -96,7 +97,7 @@ class Model:
         if n <= 0:
             return
         if s > 0:
-            yield from self.wait_progress(sh, s, min(n, BLOCK + 2))
+            yield from self.wait_progress(sh, s, min(n, self.block + 2))
             assert sh.corner.get(s) == (pair, s - 1), "corner not handed over"
             # the edges of rows 0 and 1 feed lane 0 at steps 0 and 1 (loads
             # past the last row are clamped and feed masked steps only)
@@ -106,9 +107,9 @@ class Model:
         T = (n + SKEW + 1) & ~1
         t = 0
         while t < T:
-            if t % BLOCK == 0:
+            if t % self.block == 0:
                 if s > 0:
-                    yield from self.wait_progress(sh, s, min(n, t + BLOCK + 2))
+                    yield from self.wait_progress(sh, s, min(n, t + self.block + 2))
                 sh.progress[s] = max(0, min(n, t - 63))
             for u in (t, t + 1):
                 # lane 0 uses the edge of row u + 2 at step u + 2, for row u + 2
@@ -133,9 +134,9 @@ class Model:
         self.edge[(wg, row)] = (pair, s)
 
 
-def run(pairs, W, persistent, grid, seed):
+def run(pairs, W, persistent, grid, seed, block=64):
     rng = random.Random(seed)
-    model = Model(pairs, W, persistent, grid, rng)
+    model = Model(pairs, W, persistent, grid, rng, block)
     waves = []
     for wg in range(grid):
         sh = Shared(waves=W)
@@ -163,16 +164,17 @@ SHAPES = [(1, 3), (2, 2), (63, 5), (64, 4), (65, 3), (100, 9), (200, 1), (130, 2
           (0, 4), (513, 32), (70, 7), (3, 16)]
 
 
+@pytest.mark.parametrize("block", BLOCKS)
 @pytest.mark.parametrize("W", [2, 4, 8])
 @pytest.mark.parametrize("persistent", [True, False])
-def test_pipeline_protocol_random_interleavings(W, persistent):
+def test_pipeline_protocol_random_interleavings(W, persistent, block):
     """Every pair is finished exactly once, every edge load sees its left
     neighbour's value for the same pair, and no wave waits forever, for
     pairs with fewer, as many and more stripes than waves, queries shorter
     than the skew, and one or several workgroups."""
     for seed in range(6):
         grid = 1 + seed % 3
-        model = run(SHAPES, W, persistent, grid, seed)
+        model = run(SHAPES, W, persistent, grid, seed, block)
         assert model.results == {i: 1 for i in range(len(SHAPES))}
 
 
