@@ -353,21 +353,29 @@ class Engine:
             t.append(self.future[self.next_future].arrival)
         return min(t) if t else None
 
-    def run(self, idle_sleep: float = 2e-4, poll_sleep: float = 2e-5, timeout: float | None = None):
+    def run(self, idle_sleep: float = 2e-4, poll_sleep: float = 0.0, timeout: float | None = None,
+            spin: float = 1.5e-4):
+        """Serve until every read is done.  While ticks are in flight the
+        loop polls them without sleeping (poll_sleep 0).  While it waits for
+        the next chunk it sleeps until `spin` seconds before that chunk and
+        polls the clock from there: a sleep overruns by tens of microseconds
+        (timer slack), and every overrun is added to a chunk's latency.  The
+        loop therefore keeps one host core busy while reads are in flight."""
         t0 = self.clock()
         while not self.all_done() or self.inflight:
             if self.tick() == 0:
                 if timeout is not None and self.clock() - t0 > timeout:
                     raise TimeoutError("serving loop did not finish")
                 if self.inflight:
-                    time.sleep(poll_sleep)
+                    if poll_sleep > 0:
+                        time.sleep(poll_sleep)
                     continue
                 nxt = self.next_event_time()
                 if nxt is None and self.pending:
                     raise RuntimeError("reads wait for arena room that no running read will free")
                 wait = idle_sleep if nxt is None else min(max(nxt - self.clock(), 0.0), idle_sleep)
-                if wait > 0:
-                    time.sleep(wait)
+                if wait > spin:
+                    time.sleep(wait - spin)
 
     def stats(self) -> dict:
         lat = np.array([x[2] for x in self.latencies]) if self.latencies else np.zeros(1)
