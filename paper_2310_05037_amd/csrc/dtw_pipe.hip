@@ -37,11 +37,11 @@ namespace ra {
 // neighbour has published a block of rows past the 64-step skew, so each
 // stripe trails the one before by about 64 + 2 blocks of rows.  The
 // streaming extension sweeps 400-row chunks, where that lag over up to 8
-// stripes is most of a chunk's sweep: it publishes every 16 steps.  Plain
+// stripes is most of a chunk's sweep: it publishes every 8 steps.  Plain
 // batches sweep whole queries of thousands of rows and keep 64, where each
 // publication's fence and spin cost more than the shorter lag saves.
 template <bool EXT>
-constexpr int pipe_block() { return EXT ? 16 : 64; }
+constexpr int pipe_block() { return EXT ? 8 : 64; }
 constexpr uint64_t kPipeSpinTicks = 500000000ull;   // 5 s
 constexpr int kPipeMaxStripes = kMaxRegion / 2048;   // 32: stripes are at most 2048 columns wide
 static_assert(256 * kMultiMaxK <= 2048, "the pipeline's stripe arrays assume stripes of at most 2048 columns");

@@ -13,14 +13,14 @@ that each edge row a stripe loads was written by its left neighbour for
 this pair and not yet overwritten, that every pair's result is written
 exactly once after all its waves are done, and that the counters start at
 zero for every pair.  No DTW arithmetic is modelled: this is the protocol
-only, for the workgroup sizes, block lengths (16 steps in the streaming
+only, for the workgroup sizes, block lengths (8 steps in the streaming
 extension, 64 in plain batches) and pair shapes the kernel takes.
 """
 import random
 
 import pytest
 
-BLOCKS = (16, 64)    # steps between progress publications: streaming extension, plain batches
+BLOCKS = (8, 64)     # steps between progress publications: streaming extension, plain batches
 SKEW = 64            # lane 63 finishes row t - 63 at step t
 
 
